@@ -1,0 +1,238 @@
+"""Pins of the oracle's moving-boundary update (Sec. III.B Aidun destroy/create,
+Sec. III.D solute expel/refill), forces (Eq. force, electrostatic force) and the
+particle integrator, against hand-built cases and exact conservation laws."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+C19 = O.D3Q19_C
+W19 = O.D3Q19_W
+
+
+def idx(x, y, z, n):
+    return (x % n) + n * ((y % n) + n * (z % n))
+
+
+def base(n=8, ns=1, pv=True):
+    p = O.make_params(n, n, n, 1 / 6, 1.0, 0.7, (0, 0, 0), [(0.3, 1)] * ns, partial_volume=pv)
+    N = n ** 3
+    f = np.tile(W19[:, None], (1, N)).reshape(-1)
+    return p, N, f
+
+
+def test_expel_equal_shares_to_d3q19_neighbours():
+    p, N, f = base()
+    n = 8
+    c = idx(3, 4, 5, n)
+    flag_old = np.zeros(N, np.uint8)
+    flag_new = flag_old.copy()
+    flag_new[c] = 1
+    owner = np.full(N, -1, np.int32)
+    owner_new = owner.copy()
+    owner_new[c] = 0
+    rho = np.full(N, 0.1)
+    rho[c] = 1.0
+    part = [dict(x=(3.5, 4.5, 5.5), R=0.4, Z=0, M=1)]
+    _, out, _, _, counts = O.boundary_update(p, part, flag_old, owner, flag_new, owner_new, f, rho)
+    assert out[c] == 0.0
+    for cv in C19[1:]:
+        assert abs(out[idx(3 + cv[0], 4 + cv[1], 5 + cv[2], n)] - (0.1 + 1 / 18)) < 1e-15
+    assert abs(out.sum() - rho.sum()) < 1e-13
+    assert tuple(counts) == (1, 0, 0)
+
+
+def test_expel_falls_back_to_d3q27_then_pool():
+    p, N, f = base()
+    n = 8
+    flag_old = np.zeros((n, n, n), np.uint8)
+    # a 3x3x3 block of boundary cells without its 8 corners, so the centre's 18
+    # D3Q19 neighbours are boundary but its 8 corner neighbours are fluid
+    flag_old[2:5, 2:5, 2:5] = 1
+    for a in (2, 4):
+        for b in (2, 4):
+            for e in (2, 4):
+                flag_old[a, b, e] = 0
+    flag_old[3, 3, 3] = 0
+    flag_new = flag_old.copy()
+    flag_new[3, 3, 3] = 1
+    flag_old, flag_new = flag_old.reshape(-1), flag_new.reshape(-1)
+    own_old = np.where(flag_old == 1, 0, -1).astype(np.int32)
+    own_new = np.where(flag_new == 1, 0, -1).astype(np.int32)
+    c = idx(3, 3, 3, n)
+    rho = np.where(flag_old == 1, 0.0, 0.2)
+    rho[c] = 0.8
+    part = [dict(x=(3.5, 3.5, 3.5), R=0.5, Z=0, M=1)]
+    _, out, _, _, counts = O.boundary_update(p, part, flag_old, own_old, flag_new, own_new, f, rho)
+    corners = [idx(3 + a, 3 + b, 3 + e, n) for a in (-1, 1) for b in (-1, 1) for e in (-1, 1)]
+    for q in corners:
+        assert abs(out[q] - (0.2 + 0.8 / 8)) < 1e-15
+    assert out[c] == 0.0 and abs(out.sum() - rho.sum()) < 1e-13
+    # now close the corners too: the solute goes to the global pool
+    flag_old2 = flag_old.copy()
+    flag_old2[corners] = 1
+    flag_new2 = flag_new.copy()
+    flag_new2[corners] = 1
+    own_old2 = np.where(flag_old2 == 1, 0, -1).astype(np.int32)
+    own_new2 = np.where(flag_new2 == 1, 0, -1).astype(np.int32)
+    rho2 = np.where(flag_old2 == 1, 0.0, 0.2)
+    rho2[c] = 0.8
+    _, out2, _, _, counts2 = O.boundary_update(p, part, flag_old2, own_old2, flag_new2, own_new2, f, rho2)
+    stable = (flag_old2 == 0) & (flag_new2 == 0)
+    assert np.allclose(out2[stable], 0.2 + 0.8 / stable.sum(), rtol=0, atol=1e-15)
+    assert counts2[2] == 1 and abs(out2.sum() - rho2.sum()) < 1e-13
+
+
+def test_aidun_destroy_and_create():
+    """Covered cell: its fluid momentum goes to the particle.  Vacated cell:
+    equilibrium at the surface velocity and the mean density of its stable
+    fluid neighbours; its momentum is taken from the particle."""
+    p, N, f = base()
+    n = 8
+    rng = np.random.default_rng(3)
+    f = (f.reshape(19, N) * (1 + 0.05 * rng.normal(size=(19, N)))).reshape(-1)
+    c = idx(2, 2, 2, n)
+    v = idx(5, 5, 5, n)
+    flag_old = np.zeros(N, np.uint8)
+    flag_old[v] = 1
+    flag_new = np.zeros(N, np.uint8)
+    flag_new[c] = 1
+    own_old = np.where(flag_old == 1, 0, -1).astype(np.int32)
+    own_new = np.where(flag_new == 1, 0, -1).astype(np.int32)
+    part = [dict(x=(4.0, 4.0, 4.0), R=1.0, Z=0, M=1, v=(0.01, -0.02, 0.005), w=(0.001, 0.002, -0.003))]
+    rho = np.full(N, 0.01)
+    f_out, _, Fc, Tc, counts = O.boundary_update(p, part, flag_old, own_old, flag_new, own_new, f, rho)
+    F = f.reshape(19, N)
+    p_destroy = C19.T @ F[:, c]
+    r_v = np.array([5.5, 5.5, 5.5]) - 4.0
+    vb = np.array(part[0]["v"]) + np.cross(part[0]["w"], r_v)
+    dens = [F[:, idx(5 + cv[0], 5 + cv[1], 5 + cv[2], n)].sum() for cv in C19[1:]]
+    rbar = np.mean(dens)
+    feq = O.equilibrium(np.array([rbar]), vb.reshape(3, 1))[:, 0]
+    assert np.allclose(f_out.reshape(19, N)[:, v], feq, rtol=0, atol=1e-16)
+    assert np.allclose(Fc[0], p_destroy - vb, rtol=0, atol=1e-15)
+    r_c = np.array([2.5, 2.5, 2.5]) - 4.0
+    assert np.allclose(Tc[0], np.cross(r_c, p_destroy) - np.cross(r_v, vb), rtol=0, atol=1e-15)
+    assert tuple(counts) == (1, 1, 0)
+
+
+def test_simple_scheme_refill():
+    """Eqs. refill and refill-neighbours: the vacated cell receives
+    sum rho_n/(N_f+1) from its N_f stable neighbours, each of which keeps
+    N_f/(N_f+1) of its solute."""
+    p, N, f = base(pv=False)
+    n = 8
+    v = idx(4, 4, 4, n)
+    flag_old = np.zeros(N, np.uint8)
+    flag_old[v] = 1
+    flag_old[idx(5, 4, 4, n)] = 1  # one neighbour stays boundary
+    flag_new = np.zeros(N, np.uint8)
+    flag_new[idx(5, 4, 4, n)] = 1
+    own_old = np.where(flag_old == 1, 0, -1).astype(np.int32)
+    own_new = np.where(flag_new == 1, 0, -1).astype(np.int32)
+    rng = np.random.default_rng(9)
+    rho = rng.uniform(0.01, 0.02, N)
+    rho[flag_old == 1] = 0.0
+    part = [dict(x=(5.0, 4.5, 4.5), R=1.0, Z=0, M=1)]
+    _, out, _, _, _ = O.boundary_update(p, part, flag_old, own_old, flag_new, own_new, f, rho)
+    nbrs = [idx(4 + cv[0], 4 + cv[1], 4 + cv[2], n) for cv in C19[1:] if not (cv[0] == 1 and cv[1] == 0 and cv[2] == 0)]
+    Nf = len(nbrs)
+    assert Nf == 17
+    assert abs(out[v] - sum(rho[m] for m in nbrs) / (Nf + 1)) < 1e-16
+    for m in nbrs:
+        assert abs(out[m] - rho[m] * Nf / (Nf + 1)) < 1e-16
+    assert abs(out.sum() - rho.sum()) < 1e-15
+
+
+def test_integrators_constant_force():
+    """Velocity Verlet: x_n = x0 + n v0 + a n^2 / 2; symplectic Euler:
+    x_n = x0 + n v0 + a n (n+1) / 2 (Sec. III.B)."""
+    for integ, ref in ((0, lambda n, a: n * n / 2 * a), (1, lambda n, a: n * (n + 1) / 2 * a)):
+        p = O.make_params(1000, 1000, 1000, 1 / 6, 1.0, 0.7, (0, 0, 0), [(0.1, 0)], integrator=integ)
+        pt = O.make_particles([dict(x=(100.0, 200.0, 300.0), v=(0.01, 0.0, -0.02), R=2.0, Z=0, M=4.0)])
+        F = np.array([0.004, -0.002, 0.001])
+        T = np.array([0.0, 0.0, 0.0])
+        pt[0].F[:] = F  # force of the (fictitious) previous step
+        nsteps = 50
+        for _ in range(nsteps):
+            O.move(p, pt)
+            O.finish(p, pt, F, T)
+        a = F / 4.0
+        x = np.array(pt[0].x[:])
+        expect = np.array([100.0, 200.0, 300.0]) + nsteps * np.array([0.01, 0.0, -0.02]) + ref(nsteps, a)
+        assert np.allclose(x, expect, rtol=0, atol=1e-10)
+
+
+def sim(n, parts, species=((0.3, 1, 0.01), (0.3, -1, 0.01)), E=(0.01, 0, 0), lb=0.7, charge_mode=0,
+        pv=True, integ=0, seed=5):
+    p = O.make_params(n, n, n, 1 / 6, 1.0, lb, E, [(D, z) for D, z, _ in species],
+                      partial_volume=pv, charge_mode=charge_mode, integrator=integ)
+    N = n ** 3
+    rng = np.random.default_rng(seed)
+    rho = np.concatenate([m * (1 + 0.01 * (2 * rng.uniform(size=N) - 1)) for _, _, m in species])
+    return O.OracleSim(p, parts, rho)
+
+
+@pytest.mark.parametrize("pv", [True, False])
+def test_solute_conserved_through_moving_boundaries(pv):
+    """Sec. III.D: expel (and refill) conserve every species to rounding while
+    a sphere crosses cells; densities stay non-negative."""
+    s = sim(16, [dict(x=(8.2, 8.1, 7.9), R=3.2, Z=10, M=100, v=(0.23, 0.11, -0.07), mode=1)], pv=pv)
+    tot0 = s.species_totals()
+    covered = 0
+    for _ in range(25):
+        s.step()
+        covered += s.last["covered"] + s.last["vacated"]
+        assert np.allclose(s.species_totals(), tot0, rtol=1e-14, atol=0)
+        assert s.rho.min() >= 0.0
+        assert np.all(s.density()[:, s.flag == 1] == 0.0)
+    assert covered > 50
+
+
+def test_momentum_budget_exact():
+    """Fluid momentum changes by the force density minus what the particles
+    received (bounce-back momentum exchange, Eq. force, and the Aidun
+    destroy/create impulses): P(n) - P(n-1) = sum f_ext - sum_p (F_hyd + F_cov)."""
+    s = sim(16, [dict(x=(8.0, 8.0, 8.0), R=3.5, Z=30, M=200, v=(0.05, -0.03, 0.02))], E=(0.02, 0.01, 0))
+    for _ in range(20):
+        P0 = s.fluid_momentum()
+        s.step()
+        P1 = s.fluid_momentum()
+        fsum = s.fext.reshape(3, -1).sum(axis=1)
+        Fp = (s.last["F_hyd"] + s.last["F_cov"]).sum(axis=0)
+        assert np.allclose(P1 - P0, fsum - Fp, rtol=0, atol=1e-13)
+
+
+def test_drag_opposes_motion():
+    s = sim(16, [dict(x=(8.0, 8.0, 8.0), R=3.0, Z=0, M=100, v=(0.02, 0.0, 0.0), mode=1)],
+            species=((0.3, 1, 0.0),), E=(0, 0, 0), lb=0.0)
+    for _ in range(15):
+        s.step()
+    F = s.last["F_hyd"][0] + s.last["F_cov"][0]
+    assert F[0] < 0 and abs(F[1]) < 1e-3 * abs(F[0]) and abs(F[2]) < 1e-3 * abs(F[0])
+
+
+@pytest.mark.parametrize("charge_mode", [0, 1])
+def test_isolated_charged_sphere_feels_only_external_field(charge_mode):
+    """No solute: the particle's own potential exerts no net force (the
+    Green's function is symmetric and the gradient antisymmetric), so
+    F_el = kT (sum_r rho_b) E."""
+    E = (0.013, -0.004, 0.007)
+    s = sim(16, [dict(x=(7.3, 8.6, 8.1), R=3.4, Z=25, M=100, mode=2)], species=((0.3, 1, 0.0),),
+            E=E, charge_mode=charge_mode)
+    s.step()
+    Q = s.rhob.sum()
+    if charge_mode == 1:
+        assert abs(Q - 25) < 1e-12
+    assert np.allclose(s.last["F_el"][0], Q * np.array(E), rtol=1e-11, atol=0)
+
+
+def test_fixed_uncharged_sphere_in_fluid_at_rest_stays_at_rest():
+    s = sim(12, [dict(x=(6.0, 6.0, 6.0), R=3.0, Z=0, M=100, mode=2)], species=((0.3, 1, 0.0),),
+            E=(0, 0, 0), lb=0.0)
+    f0 = s.f.copy()
+    for _ in range(3):
+        s.step()
+    fl = np.tile(s.flag == 0, 19)
+    assert np.max(np.abs(s.f[fl] - f0[fl])) < 1e-16
+    assert np.max(np.abs(s.last["F_hyd"])) < 1e-14
