@@ -1,0 +1,204 @@
+/*
+ * ek.h -- C ABI of the MI355X (gfx950) library for one time step of lattice
+ * electrokinetics with moving charged particles, after Kuron, Rempfer,
+ * Schornbaum, Bauer, Godenschwager, Holm and de Graaf, "Moving Charged
+ * Particles in Lattice Boltzmann-Based Electrokinetics" (J. Chem. Phys. 2016).
+ *
+ * One step (ek_step) advances, on the GPU only:
+ *   - the particles (Sec. III.B: velocity Verlet or symplectic Euler),
+ *   - their coverage of the lattice: boundary flags, partial volumes Psi
+ *     (Sec. III.D.2), LB fluid destroyed/created in covered/vacated cells
+ *     (Sec. III.B, after Aidun) and solute expelled from covered cells so that
+ *     every species is conserved (Sec. III.D.1),
+ *   - the charge density and the periodic Poisson equation (Eq. poisson, FFT),
+ *   - the Nernst-Planck link fluxes (Sec. III.C: diffusive + migrative with
+ *     partial-volume smoothing, Eq. flux-pv; volume-of-fluid advection), the
+ *     continuity update and the coupling force on the fluid (Eq. fluidcoupling),
+ *   - the D3Q19 TRT lattice Boltzmann stream/collide with the Guo force term
+ *     (Eq. guo) and velocity bounce-back on the particles (Sec. III.A/B),
+ *   - the momentum-exchange force and torque (Eq. force) and the electrostatic
+ *     force on each particle.
+ *
+ * Conventions
+ *   - Every function returns EK_OK (0) or a negative EK_ERR_* code; no call
+ *     throws.  ek_strerror() names a code.  A device error is latched in the
+ *     context and returned by every later call on it.
+ *   - The library owns contexts and all device memory it allocates; the caller
+ *     owns every host buffer passed in or out (it is read or written during
+ *     the call only).  Device memory may instead be provided by the caller as
+ *     an arena (e.g. a PyTorch tensor); the caller then keeps it alive and
+ *     unmodified until ek_destroy.
+ *   - Calls are ordered on the context's stream.  ek_step only enqueues work;
+ *     ek_get_* synchronise the stream before copying.
+ *   - Units: the parameters are in simulation units (agrid, tau, kT and the
+ *     fluid density fix the conversion to lattice units).  Fields and particle
+ *     state are exchanged in the same simulation units.  The potential is
+ *     e*Phi/kT.  Cell (x,y,z) is element x + nx*(y + ny*z) of a field; its
+ *     centre is at ((x+1/2) agrid, (y+1/2) agrid, (z+1/2) agrid).
+ *   - One context must not be used by two host threads at once.
+ */
+#ifndef EK_H
+#define EK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EK_MAX_SPECIES 4
+
+/* error codes */
+#define EK_OK 0
+#define EK_ERR_INVALID_ARG (-1)      /* null pointer, bad enum, size mismatch, bad value */
+#define EK_ERR_UNSUPPORTED_SIZE (-2) /* a box edge is not 2^a 3^b with a >= 1, or outside [8, 512] */
+#define EK_ERR_UNSTABLE (-3)         /* D tau/a^2 above the explicit-diffusion bound, or viscosity <= 0 */
+#define EK_ERR_OVERLAP (-4)          /* a sphere too large for the box */
+#define EK_ERR_OOM (-5)              /* device allocation failed or the arena is too small */
+#define EK_ERR_NO_SPACE (-6)         /* no free slot / memory for a batched simulation */
+#define EK_ERR_NONFINITE (-7)        /* a NaN or infinity in host input */
+#define EK_ERR_DEVICE (-8)           /* a HIP call failed (latched) */
+#define EK_ERR_STATE (-9)            /* call not allowed in the current state */
+
+/* ek_params.precision */
+#define EK_FP64_PLAIN 0   /* every field stored and stepped in FP64 */
+#define EK_FP32_DEV 1     /* FP32 storage: populations and densities as deviations
+                             from the reference values; FP64 for particle state,
+                             global sums, moving-boundary redistribution */
+/* ek_params.scheme */
+#define EK_SCHEME_PARTIAL_VOLUME 0  /* Sec. III.D.2, Eq. flux-pv */
+#define EK_SCHEME_SIMPLE 1          /* Sec. III.D.1, Eq. flux-disc with expel + refill */
+/* ek_params.charge_mode: how a particle's charge enters Poisson's equation */
+#define EK_CHARGE_PSI 0             /* rho_b = Z Psi_p / V_p (Sec. III.D.2) */
+#define EK_CHARGE_UNIFORM 1         /* Z spread equally over the particle's boundary cells */
+/* ek_params.integrator (Sec. III.B) */
+#define EK_VELOCITY_VERLET 0
+#define EK_SYMPLECTIC_EULER 1
+/* ek_add_sphere mode */
+#define EK_FREE 0                   /* moved by the forces */
+#define EK_PRESCRIBED 1             /* moves at its given velocity */
+#define EK_FIXED 2                  /* does not move (co-moving frame) */
+
+typedef struct {
+    double D;            /* diffusion coefficient D_k (Eq. flux) */
+    int valency;         /* z_k */
+    double mean_density; /* reference density rho_k (number per volume); the
+                            FP32 path stores deviations from it */
+} ek_species;
+
+typedef struct {
+    int nx, ny, nz;               /* periodic box in cells; each 2^a 3^b, a >= 1, 8..512 */
+    double agrid, tau;            /* lattice spacing and time step (Sec. III.A) */
+    double kT;                    /* thermal energy */
+    double fluid_density;         /* fluid mass density (reference density of the LB) */
+    double viscosity;             /* kinematic viscosity */
+    int n_species;                /* 1..EK_MAX_SPECIES */
+    ek_species species[EK_MAX_SPECIES];
+    double bjerrum_length;        /* lambda_B (Eq. poisson) */
+    double E_ext[3];              /* uniform external field in kT/(e * length) */
+    int precision;                /* EK_FP64_PLAIN | EK_FP32_DEV */
+    int scheme;                   /* EK_SCHEME_* */
+    int charge_mode;              /* EK_CHARGE_* */
+    int integrator;               /* EK_VELOCITY_VERLET | EK_SYMPLECTIC_EULER */
+    int max_particles;            /* capacity of ek_add_sphere (1..1024) */
+    void* stream;                 /* hipStream_t to order work on; NULL: the library creates one */
+    void* arena;                  /* optional caller device memory (>= ek_query_footprint); NULL: library allocates */
+    size_t arena_bytes;
+} ek_params;
+
+typedef struct {
+    double x[3], v[3], omega[3];  /* centre, velocity, angular velocity */
+    double F[3], T[3];            /* total force / torque of the last step */
+    double F_hyd[3], F_el[3], F_cov[3]; /* its parts: momentum exchange (Eq. force),
+                                         electrostatic, fluid destroyed/created */
+    double radius, charge, mass;
+    int mode;
+    int n_boundary;               /* cells whose centre is inside (owned) */
+} ek_particle;
+
+typedef struct {
+    long long step;
+    double species_total[EK_MAX_SPECIES]; /* FP64 sum over cells of rho_k * agrid^3 */
+    double solute_charge;                 /* sum_k z_k species_total[k] */
+    double particle_charge;               /* sum over cells of rho_b * agrid^3 */
+    double fluid_mass;                    /* sum over fluid cells of the LB density * agrid^3 */
+    double fluid_momentum[3];
+    long long covered, vacated, pooled;   /* moving-boundary events of the last step */
+    long long boundary_cells;             /* cells flagged as boundary now */
+    double max_velocity;                  /* max |u| over fluid cells (lattice units) */
+} ek_diag;
+
+typedef struct ek_ctx ek_ctx;
+
+/* field ids for ek_get_fields / ek_set_fields; sizes are in elements, x fastest */
+#define EK_FIELD_DENSITY 0        /* n_species * N doubles (species-major) */
+#define EK_FIELD_PHI 1            /* N doubles, e*Phi/kT (periodic part; E_ext is separate) */
+#define EK_FIELD_VELOCITY 2       /* 3 * N doubles, component-major; 0 in boundary cells */
+#define EK_FIELD_FLUID_DENSITY 3  /* N doubles (sum of populations) */
+#define EK_FIELD_FORCE 4          /* 3 * N doubles, coupling force density of the last step */
+#define EK_FIELD_PSI 5            /* N doubles, partial volume in [0, 1] */
+#define EK_FIELD_FLAG 6           /* N uint8: 1 boundary, 0 fluid */
+#define EK_FIELD_OWNER 7          /* N int32: owning particle id, -1 for none */
+#define EK_FIELD_POPULATIONS 8    /* 19 * N doubles, post-collision f_i (direction-major) */
+#define EK_FIELD_PARTICLE_CHARGE 9 /* N doubles, rho_b */
+
+/* Device bytes a context with these parameters needs (arena size). */
+int ek_query_footprint(const ek_params* p, size_t* bytes);
+
+/* Validate the parameters, take (or allocate) device memory and set the fluid
+ * at rest and every species at its mean density.  Errors: INVALID_ARG,
+ * UNSUPPORTED_SIZE, UNSTABLE, OOM, DEVICE. */
+int ek_create(const ek_params* p, ek_ctx** out);
+
+/* Add a sphere (Sec. III.B): centre pos, radius, valency of its charge
+ * (charge = Z in units of e), mass, initial velocity v0 (may be NULL), and mode
+ * EK_FREE / EK_PRESCRIBED / EK_FIXED.  Allowed before the first step only.
+ * Returns its id in *id (may be NULL).  Errors: INVALID_ARG, OVERLAP (2R + 2
+ * cells exceed an edge), STATE (after the first step or beyond max_particles). */
+int ek_add_sphere(ek_ctx* c, const double pos[3], double radius, double charge, double mass,
+                  const double v0[3], int mode, int* id);
+
+/* Test hook: resting walls (mask != 0) carrying an optional fixed charge
+ * density (may be NULL), both N elements.  Before the first step only. */
+int ek_set_static_boundary(ek_ctx* c, const uint8_t* mask, const double* charge);
+
+/* Overwrite a field from a host buffer of exactly the size listed above
+ * (DENSITY, PHI, VELOCITY, FORCE, POPULATIONS).  DENSITY set before the first
+ * step is the initial concentration: at preparation, boundary cells are
+ * emptied and, in the partial-volume scheme, fluid cells keep (1 - Psi) of it. */
+int ek_set_fields(ek_ctx* c, int field, const void* host, size_t bytes);
+
+/* Compute the initial coverage (flags, Psi, particle charge) and apply the
+ * initial-density rule.  Called by the first ek_step if not called before. */
+int ek_prepare(ek_ctx* c);
+
+/* Enqueue n >= 0 full time steps on the context's stream (captured once in a
+ * HIP graph and replayed).  Returns without waiting. */
+int ek_step(ek_ctx* c, int n);
+
+/* Copy a field to a host buffer of exactly the listed size (synchronises). */
+int ek_get_fields(ek_ctx* c, int field, void* host, size_t bytes);
+
+/* Copy the state of the first n particles (synchronises). */
+int ek_get_particles(ek_ctx* c, ek_particle* out, int n);
+
+/* FP64 global sums computed on the device (synchronises). */
+int ek_get_diagnostics(ek_ctx* c, ek_diag* out);
+
+/* Checkpoint: the full device state as an opaque byte image.  With host ==
+ * NULL, *bytes receives the size.  ek_set_state restores an image taken from a
+ * context created with the same parameters and particle count. */
+int ek_get_state(ek_ctx* c, void* host, size_t* bytes);
+int ek_set_state(ek_ctx* c, const void* host, size_t bytes);
+
+/* Wait for all enqueued work of the context. */
+int ek_synchronize(ek_ctx* c);
+
+int ek_destroy(ek_ctx* c);
+const char* ek_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,804 @@
+// ek_api.cpp -- host side of the C ABI declared in include/ek.h: parameter
+// validation, unit conversion, device memory layout, the per-step launch
+// sequence (captured once per ping-pong parity into HIP graphs) and the
+// host <-> device field transfers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ek_internal.h"
+
+using namespace ek;
+
+namespace {
+
+constexpr int GRAPH_CHUNK = 8;  // steps per replay of the long graph (even: parity preserved)
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+bool edge_ok(int n) {
+    if (n < 8 || n > MAX_FFT || (n & 1)) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+// Largest stable D tau / a^2 of the explicit link flux: 2 / max_k of the
+// diffusive decay rate sum_i (1 - cos k.c_i) / (A0 |c_i|), reached at
+// k = (0, pi, pi), where the sum is 8 + 8 sqrt 2.
+double d_max() {
+    const double A0 = 1.0 + 2.0 * std::sqrt(2.0);
+    return 2.0 * A0 / (8.0 + 8.0 * std::sqrt(2.0));
+}
+
+struct Layout {
+    size_t f, rho, u, fext, phi, rhob, psi, flag, owner, owner_prev, psi_owner, spec, tw, k2, parts, scratch,
+        diag, state_end, total;
+};
+
+Layout make_layout(const ek_params* p, size_t ts) {
+    Layout L{};
+    size_t N = (size_t)p->nx * p->ny * p->nz;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.f = take(2 * 19 * N * ts);
+    L.rho = take(2 * (size_t)p->n_species * N * ts);
+    L.u = take(3 * N * ts);
+    L.fext = take(3 * N * ts);
+    L.phi = take(N * ts);
+    L.rhob = take(N * ts);
+    L.psi = take(N * sizeof(float));
+    L.flag = take(N);
+    L.owner = take(N * 2);
+    L.owner_prev = take(N * 2);
+    L.psi_owner = take(N * 2);
+    int mp = p->max_particles > 0 ? p->max_particles : 1;
+    L.parts = take((size_t)mp * sizeof(PState));
+    L.state_end = off;
+    L.spec = take((size_t)(p->nx / 2 + 1) * p->ny * p->nz * 2 * ts);
+    L.tw = take((size_t)(p->nx + p->ny + p->nz) * 2 * ts);
+    L.k2 = take((size_t)(p->nx + p->ny + p->nz) * ts);
+    L.scratch = take((size_t)DIAG_BLOCKS * NDIAG * sizeof(double));
+    L.diag = take(64 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int validate(const ek_params* p) {
+    if (!p) return EK_ERR_INVALID_ARG;
+    if (!edge_ok(p->nx) || !edge_ok(p->ny) || !edge_ok(p->nz)) return EK_ERR_UNSUPPORTED_SIZE;
+    if (!(p->agrid > 0) || !(p->tau > 0) || !(p->kT > 0) || !(p->fluid_density > 0)) return EK_ERR_INVALID_ARG;
+    if (!std::isfinite(p->viscosity) || !std::isfinite(p->bjerrum_length) || p->bjerrum_length < 0)
+        return EK_ERR_INVALID_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(p->E_ext[d])) return EK_ERR_NONFINITE;
+    if (!(p->viscosity > 0)) return EK_ERR_UNSTABLE;
+    if (p->n_species < 1 || p->n_species > EK_MAX_SPECIES) return EK_ERR_INVALID_ARG;
+    for (int k = 0; k < p->n_species; ++k) {
+        const ek_species& s = p->species[k];
+        if (!std::isfinite(s.D) || !std::isfinite(s.mean_density) || s.D < 0 || s.mean_density < 0)
+            return EK_ERR_INVALID_ARG;
+        double Dl = s.D * p->tau / (p->agrid * p->agrid);
+        if (Dl > d_max() * (1.0 - 1e-3)) return EK_ERR_UNSTABLE;
+    }
+    if (p->precision != EK_FP64_PLAIN && p->precision != EK_FP32_DEV) return EK_ERR_INVALID_ARG;
+    if (p->scheme != EK_SCHEME_PARTIAL_VOLUME && p->scheme != EK_SCHEME_SIMPLE) return EK_ERR_INVALID_ARG;
+    if (p->charge_mode != EK_CHARGE_PSI && p->charge_mode != EK_CHARGE_UNIFORM) return EK_ERR_INVALID_ARG;
+    if (p->integrator != EK_VELOCITY_VERLET && p->integrator != EK_SYMPLECTIC_EULER) return EK_ERR_INVALID_ARG;
+    if (p->max_particles < 0 || p->max_particles > 1024) return EK_ERR_INVALID_ARG;
+    return EK_OK;
+}
+
+}  // namespace
+
+struct ek_ctx {
+    ek_params p{};
+    Layout L{};
+    bool fp32 = false;
+    Sim<float> sf{};
+    Sim<double> sd{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    unsigned char* arena = nullptr;
+    bool own_arena = false;
+    double* wall_charge = nullptr;
+    std::vector<PState> parts;
+    bool prepared = false;
+    long long step = 0;
+    int err = EK_OK;
+    bool use_graphs = true;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    // unit conversion (simulation units per lattice unit)
+    double a = 1, tau = 1, rf = 1;
+    long N = 0;
+
+    int cur() const { return fp32 ? sf.cur : sd.cur; }
+    void set_cur(int c) {
+        sf.cur = c;
+        sd.cur = c;
+    }
+};
+
+#define HIPCHK(c, x)                      \
+    do {                                  \
+        hipError_t e_ = (x);              \
+        if (e_ != hipSuccess) {           \
+            (c)->err = EK_ERR_DEVICE;     \
+            return EK_ERR_DEVICE;         \
+        }                                 \
+    } while (0)
+
+namespace {
+
+template <typename T>
+void setup_sim(ek_ctx* c, Sim<T>& s) {
+    const ek_params* p = &c->p;
+    unsigned char* A = c->arena;
+    const Layout& L = c->L;
+    long N = c->N;
+    s.nx = p->nx;
+    s.ny = p->ny;
+    s.nz = p->nz;
+    s.nxh = p->nx / 2 + 1;
+    s.N = N;
+    s.Nspec = (long)s.nxh * p->ny * p->nz;
+    s.ns = p->n_species;
+    s.np = 0;
+    s.pv = p->scheme == EK_SCHEME_PARTIAL_VOLUME;
+    s.charge_mode = p->charge_mode;
+    s.integrator = p->integrator;
+    s.cur = 0;
+    const double a = p->agrid, tau = p->tau, rf = p->fluid_density;
+    s.kT = p->kT * tau * tau / (rf * a * a * a * a * a);
+    s.lambda_B = p->bjerrum_length / a;
+    for (int d = 0; d < 3; ++d) s.E[d] = p->E_ext[d] * a;
+    for (int k = 0; k < MAXS; ++k) s.D[k] = s.z[k] = s.rho_ref[k] = 0.0;
+    for (int k = 0; k < p->n_species; ++k) {
+        s.D[k] = p->species[k].D * tau / (a * a);
+        s.z[k] = p->species[k].valency;
+        s.rho_ref[k] = sizeof(T) == 4 ? p->species[k].mean_density * a * a * a : 0.0;
+    }
+    double nu = p->viscosity * tau / (a * a);
+    double tp = 3.0 * nu + 0.5;
+    double tm = 0.5 + (3.0 / 16.0) / (tp - 0.5);
+    s.lam_e = (T)(-1.0 / tp);
+    s.lam_o = (T)(-1.0 / tm);
+    s.n_wall = 0;
+    size_t ts = sizeof(T);
+    s.f[0] = (T*)(A + L.f);
+    s.f[1] = s.f[0] + 19 * N;
+    s.rho[0] = (T*)(A + L.rho);
+    s.rho[1] = s.rho[0] + (long)p->n_species * N;
+    s.u = (T*)(A + L.u);
+    s.fext = (T*)(A + L.fext);
+    s.phi = (T*)(A + L.phi);
+    s.rhob = (T*)(A + L.rhob);
+    s.psi = (float*)(A + L.psi);
+    s.flag = A + L.flag;
+    s.owner = (uint16_t*)(A + L.owner);
+    s.owner_prev = (uint16_t*)(A + L.owner_prev);
+    s.psi_owner = (uint16_t*)(A + L.psi_owner);
+    s.wall_charge = nullptr;
+    s.spec = (T*)(A + L.spec);
+    T* tw = (T*)(A + L.tw);
+    T* k2 = (T*)(A + L.k2);
+    s.tw[0] = tw;
+    s.tw[1] = tw + 2 * p->nx;
+    s.tw[2] = tw + 2 * (p->nx + p->ny);
+    s.k2[0] = k2;
+    s.k2[1] = k2 + p->nx;
+    s.k2[2] = k2 + p->nx + p->ny;
+    s.parts = (PState*)(A + L.parts);
+    s.scratch = (double*)(A + L.scratch);
+    s.box_max = 0;
+    (void)ts;
+}
+
+template <typename T>
+int init_fields(ek_ctx* c, Sim<T>& s) {
+    const ek_params* p = &c->p;
+    hipStream_t st = c->stream;
+    long N = c->N;
+    bool dev = sizeof(T) == 4;
+    for (int b = 0; b < 2; ++b)
+        for (int i = 0; i < 19; ++i) fill<T>(s.f[b] + (long)i * N, N, dev ? (T)0 : (T)q19w(i), st);
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < p->n_species; ++k)
+            fill<T>(s.rho[b] + (long)k * N, N,
+                    dev ? (T)0 : (T)(p->species[k].mean_density * p->agrid * p->agrid * p->agrid), st);
+    fill<T>(s.u, 3 * N, (T)0, st);
+    fill<T>(s.fext, 3 * N, (T)0, st);
+    fill<T>(s.phi, N, (T)0, st);
+    fill<T>(s.rhob, N, (T)0, st);
+    fill<float>(s.psi, N, 0.0f, st);
+    fill<uint8_t>(s.flag, N, (uint8_t)0, st);
+    fill<uint16_t>(s.owner, N, NO_OWNER, st);
+    fill<uint16_t>(s.owner_prev, N, NO_OWNER, st);
+    fill<uint16_t>(s.psi_owner, N, NO_OWNER, st);
+    // FFT tables in FP64 on the host, rounded once to T
+    int n[3] = {p->nx, p->ny, p->nz};
+    std::vector<T> tw, k2;
+    for (int d = 0; d < 3; ++d)
+        for (int m = 0; m < n[d]; ++m) {
+            double ang = 2.0 * M_PI * (double)m / (double)n[d];
+            tw.push_back((T)std::cos(ang));
+            tw.push_back((T)-std::sin(ang));
+            k2.push_back((T)(2.0 - 2.0 * std::cos(ang)));
+        }
+    HIPCHK(c, hipMemcpyAsync(s.tw[0], tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(s.k2[0], k2.data(), k2.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    HIPCHK(c, hipGetLastError());
+    return EK_OK;
+}
+
+template <typename T>
+void enqueue_step(const ek_ctx* c, Sim<T> s) {
+    hipStream_t st = c->stream;
+    launch_move(s, st, 0);
+    launch_geometry(s, st, 0);
+    launch_boundary(s, st);
+    if (!s.pv) launch_refill(s, st);
+    launch_charge_poisson(s, st);
+    launch_ek(s, st);
+    launch_hydro(s, st);
+    launch_lb(s, st);
+    launch_forces(s, st);
+    launch_finish(s, st);
+}
+
+template <typename T>
+int build_graph(ek_ctx* c, Sim<T> s, int parity, int nsteps, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < nsteps; ++k) {
+        s.cur = (parity + k) & 1;
+        enqueue_step(c, s);
+    }
+    HIPCHK(c, hipStreamEndCapture(c->stream, &g));
+    hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(c, e);
+    return EK_OK;
+}
+
+template <typename T>
+int run_steps(ek_ctx* c, Sim<T>& s, int n) {
+    while (n > 0) {
+        int par = s.cur;
+        int chunk = (n >= GRAPH_CHUNK) ? 1 : 0;
+        int k = chunk ? GRAPH_CHUNK : 1;
+        if (c->use_graphs) {
+            if (!c->graph[par][chunk]) {
+                int r = build_graph(c, s, par, k, &c->graph[par][chunk]);
+                if (r) return r;
+            }
+            HIPCHK(c, hipGraphLaunch(c->graph[par][chunk], c->stream));
+        } else {
+            Sim<T> t = s;
+            for (int i = 0; i < k; ++i) {
+                t.cur = (par + i) & 1;
+                enqueue_step(c, t);
+            }
+            HIPCHK(c, hipGetLastError());
+        }
+        if (k & 1) c->set_cur(par ^ 1);
+        c->step += k;
+        n -= k;
+    }
+    return EK_OK;
+}
+
+template <typename T>
+int prepare(ek_ctx* c, Sim<T>& s) {
+    hipStream_t st = c->stream;
+    int np = (int)c->parts.size();
+    int box_max = 0;
+    int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+    for (const PState& q : c->parts) {
+        int b = 1;
+        for (int d = 0; d < 3; ++d) {
+            int e = (int)std::ceil(2.0 * q.R) + 2 * BOX_MARGIN + 4;
+            b *= e < n[d] ? e : n[d];
+        }
+        box_max = b > box_max ? b : box_max;
+    }
+    c->sf.np = c->sd.np = np;
+    c->sf.box_max = c->sd.box_max = box_max;
+    if (np > 0)
+        HIPCHK(c, hipMemcpyAsync(s.parts, c->parts.data(), np * sizeof(PState), hipMemcpyHostToDevice, st));
+    Sim<T> t = s;
+    launch_move(t, st, 1);
+    launch_geometry(t, st, 1);
+    launch_init_density(t, st);
+    launch_boundary(t, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->prepared = true;
+    return EK_OK;
+}
+
+// conversion factors: simulation value = lattice value * factor
+double field_factor(const ek_ctx* c, int field) {
+    double a = c->a, tau = c->tau, rf = c->rf;
+    switch (field) {
+        case EK_FIELD_DENSITY: return 1.0 / (a * a * a);
+        case EK_FIELD_PHI: return 1.0;
+        case EK_FIELD_VELOCITY: return a / tau;
+        case EK_FIELD_FLUID_DENSITY: return rf;
+        case EK_FIELD_FORCE: return rf * a / (tau * tau);
+        case EK_FIELD_PSI: return 1.0;
+        case EK_FIELD_POPULATIONS: return rf;
+        case EK_FIELD_PARTICLE_CHARGE: return 1.0 / (a * a * a);
+        default: return 1.0;
+    }
+}
+
+long field_elems(const ek_ctx* c, int field) {
+    long N = c->N;
+    switch (field) {
+        case EK_FIELD_DENSITY: return (long)c->p.n_species * N;
+        case EK_FIELD_VELOCITY:
+        case EK_FIELD_FORCE: return 3 * N;
+        case EK_FIELD_POPULATIONS: return 19 * N;
+        case EK_FIELD_PHI:
+        case EK_FIELD_FLUID_DENSITY:
+        case EK_FIELD_PSI:
+        case EK_FIELD_FLAG:
+        case EK_FIELD_OWNER:
+        case EK_FIELD_PARTICLE_CHARGE: return N;
+        default: return -1;
+    }
+}
+
+template <typename T>
+int get_field(ek_ctx* c, Sim<T>& s, int field, void* host, size_t bytes) {
+    long ne = field_elems(c, field);
+    if (ne < 0) return EK_ERR_INVALID_ARG;
+    long N = c->N;
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipStreamSynchronize(st));
+    bool dev = sizeof(T) == 4;
+    double fac = field_factor(c, field);
+    if (field == EK_FIELD_FLAG) {
+        if (bytes != (size_t)N) return EK_ERR_INVALID_ARG;
+        std::vector<uint8_t> h(N);
+        HIPCHK(c, hipMemcpy(h.data(), s.flag, N, hipMemcpyDeviceToHost));
+        uint8_t* o = (uint8_t*)host;
+        for (long i = 0; i < N; ++i) o[i] = (h[i] & F_CUR) ? 1 : 0;
+        return EK_OK;
+    }
+    if (field == EK_FIELD_OWNER) {
+        if (bytes != (size_t)N * sizeof(int32_t)) return EK_ERR_INVALID_ARG;
+        std::vector<uint16_t> h(N);
+        std::vector<uint8_t> fl(N);
+        HIPCHK(c, hipMemcpy(h.data(), s.owner, N * 2, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(fl.data(), s.flag, N, hipMemcpyDeviceToHost));
+        int32_t* o = (int32_t*)host;
+        for (long i = 0; i < N; ++i) o[i] = ((fl[i] & F_CUR) && h[i] != NO_OWNER) ? (int32_t)h[i] : -1;
+        return EK_OK;
+    }
+    if (bytes != (size_t)ne * sizeof(double)) return EK_ERR_INVALID_ARG;
+    double* o = (double*)host;
+    if (field == EK_FIELD_PSI) {
+        std::vector<float> h(N);
+        HIPCHK(c, hipMemcpy(h.data(), s.psi, N * sizeof(float), hipMemcpyDeviceToHost));
+        for (long i = 0; i < N; ++i) o[i] = h[i];
+        return EK_OK;
+    }
+    std::vector<T> h;
+    const T* src = nullptr;
+    int cur = s.cur;
+    switch (field) {
+        case EK_FIELD_DENSITY: src = s.rho[cur]; break;
+        case EK_FIELD_PHI: src = s.phi; break;
+        case EK_FIELD_VELOCITY: src = s.u; break;
+        case EK_FIELD_FORCE: src = s.fext; break;
+        case EK_FIELD_POPULATIONS:
+        case EK_FIELD_FLUID_DENSITY: src = s.f[cur]; break;
+        case EK_FIELD_PARTICLE_CHARGE: src = s.rhob; break;
+    }
+    long nsrc = field == EK_FIELD_FLUID_DENSITY ? 19 * N : ne;
+    h.resize(nsrc);
+    HIPCHK(c, hipMemcpy(h.data(), src, nsrc * sizeof(T), hipMemcpyDeviceToHost));
+    if (field == EK_FIELD_DENSITY) {
+        for (int k = 0; k < c->p.n_species; ++k)
+            for (long i = 0; i < N; ++i) o[k * N + i] = ((dev ? s.rho_ref[k] : 0.0) + (double)h[k * N + i]) * fac;
+    } else if (field == EK_FIELD_POPULATIONS) {
+        for (int q = 0; q < 19; ++q)
+            for (long i = 0; i < N; ++i) o[q * N + i] = ((dev ? q19w(q) : 0.0) + (double)h[q * N + i]) * fac;
+    } else if (field == EK_FIELD_FLUID_DENSITY) {
+        for (long i = 0; i < N; ++i) {
+            double m = dev ? 1.0 : 0.0;
+            for (int q = 0; q < 19; ++q) m += (double)h[q * N + i];
+            o[i] = m * fac;
+        }
+    } else {
+        for (long i = 0; i < ne; ++i) o[i] = (double)h[i] * fac;
+    }
+    return EK_OK;
+}
+
+template <typename T>
+int set_field(ek_ctx* c, Sim<T>& s, int field, const void* host, size_t bytes) {
+    long ne = field_elems(c, field);
+    long N = c->N;
+    if (ne < 0 || bytes != (size_t)ne * sizeof(double)) return EK_ERR_INVALID_ARG;
+    const double* in = (const double*)host;
+    for (long i = 0; i < ne; ++i)
+        if (!std::isfinite(in[i])) return EK_ERR_NONFINITE;
+    bool dev = sizeof(T) == 4;
+    double fac = field_factor(c, field);
+    std::vector<T> h(ne);
+    T* dst = nullptr;
+    int cur = s.cur;
+    switch (field) {
+        case EK_FIELD_DENSITY:
+            dst = s.rho[cur];
+            for (int k = 0; k < c->p.n_species; ++k)
+                for (long i = 0; i < N; ++i) h[k * N + i] = (T)(in[k * N + i] / fac - (dev ? s.rho_ref[k] : 0.0));
+            break;
+        case EK_FIELD_POPULATIONS:
+            dst = s.f[cur];
+            for (int q = 0; q < 19; ++q)
+                for (long i = 0; i < N; ++i) h[q * N + i] = (T)(in[q * N + i] / fac - (dev ? q19w(q) : 0.0));
+            break;
+        case EK_FIELD_PHI: dst = s.phi; break;
+        case EK_FIELD_VELOCITY: dst = s.u; break;
+        case EK_FIELD_FORCE: dst = s.fext; break;
+        default: return EK_ERR_INVALID_ARG;
+    }
+    if (field == EK_FIELD_PHI || field == EK_FIELD_VELOCITY || field == EK_FIELD_FORCE)
+        for (long i = 0; i < ne; ++i) h[i] = (T)(in[i] / fac);
+    HIPCHK(c, hipMemcpyAsync(dst, h.data(), ne * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return EK_OK;
+}
+
+template <typename T>
+int diagnostics(ek_ctx* c, Sim<T>& s, ek_diag* out) {
+    double* dout = (double*)(c->arena + c->L.diag);
+    launch_diagnostics(s, c->stream, dout);
+    HIPCHK(c, hipGetLastError());
+    double h[NDIAG];
+    HIPCHK(c, hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double a = c->a, tau = c->tau, rf = c->rf;
+    std::memset(out, 0, sizeof(*out));
+    out->step = c->step;
+    for (int k = 0; k < c->p.n_species; ++k) {
+        out->species_total[k] = h[k];
+        out->solute_charge += c->p.species[k].valency * h[k];
+    }
+    out->particle_charge = h[MAXS];
+    out->fluid_mass = h[MAXS + 1] * rf * a * a * a;
+    for (int d = 0; d < 3; ++d) out->fluid_momentum[d] = h[MAXS + 2 + d] * rf * a * a * a * a / tau;
+    out->boundary_cells = (long long)h[MAXS + 5];
+    out->max_velocity = h[MAXS + 6];
+    int np = (int)c->parts.size();
+    if (np > 0 && c->prepared) {
+        std::vector<PState> ps(np);
+        HIPCHK(c, hipMemcpy(ps.data(), s.parts, np * sizeof(PState), hipMemcpyDeviceToHost));
+        for (const PState& q : ps) {
+            out->covered += q.ncov;
+            out->vacated += q.nvac;
+            out->pooled += q.npool;
+        }
+    }
+    return EK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ek_strerror(int code) {
+    switch (code) {
+        case EK_OK: return "ok";
+        case EK_ERR_INVALID_ARG: return "invalid argument";
+        case EK_ERR_UNSUPPORTED_SIZE: return "unsupported box size (each edge 2^a 3^b, a >= 1, 8..512)";
+        case EK_ERR_UNSTABLE: return "parameters outside the stability range";
+        case EK_ERR_OVERLAP: return "sphere too large for the box";
+        case EK_ERR_OOM: return "out of device memory";
+        case EK_ERR_NO_SPACE: return "no free slot or memory";
+        case EK_ERR_NONFINITE: return "non-finite input";
+        case EK_ERR_DEVICE: return "HIP device error";
+        case EK_ERR_STATE: return "call not allowed in the current state";
+        default: return "unknown error";
+    }
+}
+
+int ek_query_footprint(const ek_params* p, size_t* bytes) {
+    int r = validate(p);
+    if (r) return r;
+    if (!bytes) return EK_ERR_INVALID_ARG;
+    *bytes = make_layout(p, p->precision == EK_FP32_DEV ? 4 : 8).total;
+    return EK_OK;
+}
+
+int ek_create(const ek_params* p, ek_ctx** out) {
+    if (!out) return EK_ERR_INVALID_ARG;
+    *out = nullptr;
+    int r = validate(p);
+    if (r) return r;
+    ek_ctx* c = new (std::nothrow) ek_ctx();
+    if (!c) return EK_ERR_OOM;
+    c->p = *p;
+    c->fp32 = p->precision == EK_FP32_DEV;
+    c->L = make_layout(p, c->fp32 ? 4 : 8);
+    c->N = (long)p->nx * p->ny * p->nz;
+    c->a = p->agrid;
+    c->tau = p->tau;
+    c->rf = p->fluid_density;
+    c->use_graphs = std::getenv("EK_DISABLE_GRAPHS") == nullptr;
+    if (p->stream) {
+        c->stream = (hipStream_t)p->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return EK_ERR_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    if (p->arena) {
+        if (p->arena_bytes < c->L.total) {
+            ek_destroy(c);
+            return EK_ERR_OOM;
+        }
+        c->arena = (unsigned char*)p->arena;
+    } else {
+        if (hipMalloc(&c->arena, c->L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            c->arena = nullptr;
+            ek_destroy(c);
+            return EK_ERR_OOM;
+        }
+        c->own_arena = true;
+    }
+    c->p.arena = c->arena;
+    c->p.arena_bytes = c->L.total;
+    setup_sim(c, c->sf);
+    setup_sim(c, c->sd);
+    r = c->fp32 ? init_fields(c, c->sf) : init_fields(c, c->sd);
+    if (r) {
+        ek_destroy(c);
+        return r;
+    }
+    *out = c;
+    return EK_OK;
+}
+
+int ek_add_sphere(ek_ctx* c, const double pos[3], double radius, double charge, double mass, const double v0[3],
+                  int mode, int* id) {
+    if (!c || !pos) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    if (c->prepared) return EK_ERR_STATE;
+    if ((int)c->parts.size() >= c->p.max_particles) return EK_ERR_STATE;
+    if (mode != EK_FREE && mode != EK_PRESCRIBED && mode != EK_FIXED) return EK_ERR_INVALID_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(pos[d]) || (v0 && !std::isfinite(v0[d]))) return EK_ERR_NONFINITE;
+    if (!std::isfinite(radius) || !std::isfinite(charge) || !std::isfinite(mass)) return EK_ERR_NONFINITE;
+    if (!(radius > 0) || (mode == EK_FREE && !(mass > 0))) return EK_ERR_INVALID_ARG;
+    double a = c->a, tau = c->tau, rf = c->rf;
+    double R = radius / a;
+    int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+    // cells within R + 1 of the centre must have a unique periodic image
+    for (int d = 0; d < 3; ++d)
+        if (2.0 * R + 2.0 > n[d]) return EK_ERR_OVERLAP;
+    PState q;
+    std::memset(&q, 0, sizeof(q));
+    for (int d = 0; d < 3; ++d) {
+        double x = pos[d] / a;
+        x = x - n[d] * std::floor(x / n[d]);
+        if (x >= n[d]) x -= n[d];
+        q.x[d] = x;
+        q.v[d] = (v0 && mode != EK_FIXED) ? v0[d] * tau / a : 0.0;
+        if (std::fabs(q.v[d]) >= 1.0) return EK_ERR_UNSTABLE;
+    }
+    q.R = R;
+    q.Z = charge;
+    q.M = mass > 0 ? mass / (rf * a * a * a) : 1.0;
+    q.I = 0.4 * q.M * q.R * q.R;
+    q.Vp = 4.0 / 3.0 * M_PI * R * R * R;
+    q.mode = mode;
+    if (id) *id = (int)c->parts.size();
+    c->parts.push_back(q);
+    return EK_OK;
+}
+
+int ek_set_static_boundary(ek_ctx* c, const uint8_t* mask, const double* charge) {
+    if (!c || !mask) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    if (c->prepared) return EK_ERR_STATE;
+    long N = c->N;
+    std::vector<uint8_t> fl(N);
+    long nw = 0;
+    for (long i = 0; i < N; ++i) {
+        fl[i] = mask[i] ? (uint8_t)(F_WALL | F_CUR | F_PREV) : (uint8_t)0;
+        nw += mask[i] ? 1 : 0;
+    }
+    uint8_t* dflag = c->fp32 ? c->sf.flag : c->sd.flag;
+    HIPCHK(c, hipMemcpy(dflag, fl.data(), N, hipMemcpyHostToDevice));
+    c->sf.n_wall = c->sd.n_wall = nw;
+    if (charge) {
+        std::vector<double> q(N);
+        for (long i = 0; i < N; ++i) {
+            if (!std::isfinite(charge[i])) return EK_ERR_NONFINITE;
+            q[i] = charge[i] * c->a * c->a * c->a;
+        }
+        if (!c->wall_charge) HIPCHK(c, hipMalloc(&c->wall_charge, N * sizeof(double)));
+        HIPCHK(c, hipMemcpy(c->wall_charge, q.data(), N * sizeof(double), hipMemcpyHostToDevice));
+        c->sf.wall_charge = c->sd.wall_charge = c->wall_charge;
+        if (c->fp32) {
+            std::vector<float> h(q.begin(), q.end());
+            HIPCHK(c, hipMemcpy(c->sf.rhob, h.data(), N * sizeof(float), hipMemcpyHostToDevice));
+        } else {
+            HIPCHK(c, hipMemcpy(c->sd.rhob, q.data(), N * sizeof(double), hipMemcpyHostToDevice));
+        }
+    }
+    return EK_OK;
+}
+
+int ek_set_fields(ek_ctx* c, int field, const void* host, size_t bytes) {
+    if (!c || !host) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    return c->fp32 ? set_field(c, c->sf, field, host, bytes) : set_field(c, c->sd, field, host, bytes);
+}
+
+int ek_prepare(ek_ctx* c) {
+    if (!c) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    if (c->prepared) return EK_OK;
+    return c->fp32 ? prepare(c, c->sf) : prepare(c, c->sd);
+}
+
+int ek_step(ek_ctx* c, int n) {
+    if (!c || n < 0) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    if (!c->prepared) {
+        int r = ek_prepare(c);
+        if (r) return r;
+    }
+    return c->fp32 ? run_steps(c, c->sf, n) : run_steps(c, c->sd, n);
+}
+
+int ek_synchronize(ek_ctx* c) {
+    if (!c) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return EK_OK;
+}
+
+int ek_get_fields(ek_ctx* c, int field, void* host, size_t bytes) {
+    if (!c || !host) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    return c->fp32 ? get_field(c, c->sf, field, host, bytes) : get_field(c, c->sd, field, host, bytes);
+}
+
+int ek_get_particles(ek_ctx* c, ek_particle* out, int n) {
+    if (!c || (!out && n > 0) || n < 0 || n > (int)c->parts.size()) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    std::vector<PState> ps(c->parts.size());
+    if (c->prepared && !ps.empty()) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        PState* dp = c->fp32 ? c->sf.parts : c->sd.parts;
+        HIPCHK(c, hipMemcpy(ps.data(), dp, ps.size() * sizeof(PState), hipMemcpyDeviceToHost));
+    } else {
+        ps = c->parts;
+    }
+    double a = c->a, tau = c->tau, rf = c->rf;
+    double fF = rf * a * a * a * a / (tau * tau), fT = fF * a;
+    for (int k = 0; k < n; ++k) {
+        const PState& q = ps[k];
+        ek_particle& o = out[k];
+        std::memset(&o, 0, sizeof(o));
+        for (int d = 0; d < 3; ++d) {
+            o.x[d] = q.x[d] * a;
+            o.v[d] = q.v[d] * a / tau;
+            o.omega[d] = q.w[d] / tau;
+            o.F[d] = q.F[d] * fF;
+            o.T[d] = q.T[d] * fT;
+            o.F_hyd[d] = q.Fh[d] * fF;
+            o.F_el[d] = q.Fe[d] * fF;
+            o.F_cov[d] = q.Fc[d] * fF;
+        }
+        o.radius = q.R * a;
+        o.charge = q.Z;
+        o.mass = q.M * rf * a * a * a;
+        o.mode = q.mode;
+        o.n_boundary = q.nb;
+    }
+    return EK_OK;
+}
+
+int ek_get_diagnostics(ek_ctx* c, ek_diag* out) {
+    if (!c || !out) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    return c->fp32 ? diagnostics(c, c->sf, out) : diagnostics(c, c->sd, out);
+}
+
+struct StateHeader {
+    uint64_t magic;
+    int64_t bytes, step;
+    int32_t cur, prepared, np, precision;
+};
+static const uint64_t STATE_MAGIC = 0x454b53544154453aULL;
+
+int ek_get_state(ek_ctx* c, void* host, size_t* bytes) {
+    if (!c || !bytes) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    size_t need = sizeof(StateHeader) + c->L.state_end + (c->wall_charge ? c->N * sizeof(double) : 0);
+    if (!host) {
+        *bytes = need;
+        return EK_OK;
+    }
+    if (*bytes < need) return EK_ERR_INVALID_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    StateHeader h{STATE_MAGIC, (int64_t)need, c->step, c->cur(), c->prepared ? 1 : 0, (int32_t)c->parts.size(),
+                  c->p.precision};
+    std::memcpy(host, &h, sizeof(h));
+    unsigned char* dst = (unsigned char*)host + sizeof(h);
+    HIPCHK(c, hipMemcpy(dst, c->arena, c->L.state_end, hipMemcpyDeviceToHost));
+    if (c->wall_charge)
+        HIPCHK(c, hipMemcpy(dst + c->L.state_end, c->wall_charge, c->N * sizeof(double), hipMemcpyDeviceToHost));
+    *bytes = need;
+    return EK_OK;
+}
+
+int ek_set_state(ek_ctx* c, const void* host, size_t bytes) {
+    if (!c || !host || bytes < sizeof(StateHeader)) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    StateHeader h;
+    std::memcpy(&h, host, sizeof(h));
+    size_t need = sizeof(StateHeader) + c->L.state_end + (c->wall_charge ? c->N * sizeof(double) : 0);
+    if (h.magic != STATE_MAGIC || (size_t)h.bytes != bytes || bytes != need || h.np != (int)c->parts.size() ||
+        h.precision != c->p.precision)
+        return EK_ERR_INVALID_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const unsigned char* src = (const unsigned char*)host + sizeof(h);
+    HIPCHK(c, hipMemcpy(c->arena, src, c->L.state_end, hipMemcpyHostToDevice));
+    if (c->wall_charge)
+        HIPCHK(c, hipMemcpy(c->wall_charge, src + c->L.state_end, c->N * sizeof(double), hipMemcpyHostToDevice));
+    c->step = h.step;
+    c->set_cur(h.cur);
+    if (h.prepared && !c->prepared) {
+        int np = (int)c->parts.size();
+        int box_max = 0;
+        int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+        for (const PState& q : c->parts) {
+            int b = 1;
+            for (int d = 0; d < 3; ++d) {
+                int e = (int)std::ceil(2.0 * q.R) + 2 * BOX_MARGIN + 4;
+                b *= e < n[d] ? e : n[d];
+            }
+            box_max = b > box_max ? b : box_max;
+        }
+        c->sf.np = c->sd.np = np;
+        c->sf.box_max = c->sd.box_max = box_max;
+        c->prepared = true;
+    }
+    return EK_OK;
+}
+
+int ek_destroy(ek_ctx* c) {
+    if (!c) return EK_ERR_INVALID_ARG;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            if (c->graph[i][j]) (void)hipGraphExecDestroy(c->graph[i][j]);
+    if (c->own_arena && c->arena) (void)hipFree(c->arena);
+    if (c->wall_charge) (void)hipFree(c->wall_charge);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return EK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// ek_internal.h -- device state layout and helpers of the gfx950 library.
+//
+// Layout in HBM (per simulation, N = nx*ny*nz cells, x fastest):
+//   f[2][19][N]   populations, ping-pong (T = double, or float deviations f - w_i)
+//   rho[2][ns][N] solute densities, ping-pong (float path: deviation from the mean)
+//   u[3][N], fext[3][N], phi[N], rhob[N]         (T)
+//   psi[N] float  (multiples of 1/4096: exact in float)
+//   flag[N] u8    bit0 boundary now, bit1 boundary before this step's move, bit2 wall
+//   owner[N], owner_prev[N], psi_owner[N] u16
+//   spec[(nx/2+1)*ny*nz] complex T  (half spectrum for the Poisson solve)
+//   FFT tables, particle records (FP64), reduction scratch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+#include "../../include/ek.h"
+
+namespace ek {
+
+constexpr int MAXS = EK_MAX_SPECIES;
+constexpr uint16_t NO_OWNER = 0xFFFF;
+constexpr uint16_t MULTI_OWNER = 0xFFFE;
+constexpr uint8_t F_CUR = 1, F_PREV = 2, F_WALL = 4;
+constexpr int BOX_MARGIN = 2;
+constexpr int MAX_FFT = 512;
+constexpr int NDIAG = MAXS + 7;       // species totals, rho_b, fluid mass, momentum(3), boundary cells, max|u|
+constexpr int DIAG_BLOCKS = 1024;
+
+// ---------------------------------------------------------------------------
+// Compile-time loops and lattice tables
+// ---------------------------------------------------------------------------
+template <typename F, int... I>
+__device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// D3Q19: rest; +-x, +-y, +-z; 12 edges as opposite pairs.
+constexpr int q19x(int i) {
+    constexpr int t[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return t[i];
+}
+constexpr int q19y(int i) {
+    constexpr int t[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return t[i];
+}
+constexpr int q19z(int i) {
+    constexpr int t[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return t[i];
+}
+constexpr int q19opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+constexpr double q19w(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+// Half of the 26-neighbourhood: 9 D3Q19 links first, then the 4 body diagonals.
+constexpr int hx(int h) {
+    constexpr int t[13] = {1, 0, 0, 1, 1, 1, 1, 0, 0, 1, 1, 1, 1};
+    return t[h];
+}
+constexpr int hy(int h) {
+    constexpr int t[13] = {0, 1, 0, 1, -1, 0, 0, 1, 1, 1, 1, -1, -1};
+    return t[h];
+}
+constexpr int hz(int h) {
+    constexpr int t[13] = {0, 0, 1, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+    return t[h];
+}
+constexpr double hlen(int h) {
+    return h < 3 ? 1.0 : (h < 9 ? 1.4142135623730950488 : 1.7320508075688772935);
+}
+
+// ---------------------------------------------------------------------------
+// Particle record (always FP64; small)
+// ---------------------------------------------------------------------------
+struct PState {
+    double x[3], v[3], w[3];
+    double R, Z, M, I, Vp;
+    double F[3], T[3];     // total of the last completed step (carried to the next kick)
+    double Fh[3], Th[3];   // momentum exchange (this step)
+    double Fe[3], Te[3];   // electrostatic (this step)
+    double Fc[3], Tc[3];   // fluid destroyed / created (this step)
+    double disp[3];        // displacement of this step's move
+    double pool[MAXS];     // solute of covered cells with no stable-fluid neighbour
+    int box_lo[3], box_n[3];
+    int mode, nb;          // nb: cells owned (centre inside)
+    int ncov, nvac, npool, nflag;  // event counts of this step; nflag: box cells flagged now or before
+};
+
+// Everything a kernel needs about one simulation (passed by value).
+template <typename T>
+struct Sim {
+    int nx, ny, nz, nxh;
+    long N, Nspec;
+    int ns, np;
+    int pv, charge_mode, integrator;
+    int cur;                  // ping-pong index of f and rho holding the current state
+    double kT, lambda_B, E[3];
+    double D[MAXS], z[MAXS], rho_ref[MAXS];
+    T lam_e, lam_o;
+    long n_wall;              // number of wall cells
+    T* f[2];
+    T* rho[2];
+    T* u;
+    T* fext;
+    T* phi;
+    T* rhob;
+    float* psi;
+    uint8_t* flag;
+    uint16_t* owner;
+    uint16_t* owner_prev;
+    uint16_t* psi_owner;
+    double* wall_charge;      // nullable
+    T* spec;                  // interleaved complex
+    T* tw[3];                 // twiddles e^{-2 pi i m/n}, interleaved, per axis
+    T* k2[3];                 // 2 - 2 cos(2 pi m / n) per axis
+    PState* parts;
+    double* scratch;          // reductions
+    int box_max;              // bound on cells of one particle box
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Minimum-image displacement along one axis, same operation order on every
+// path that decides coverage (no contraction: see the pragma at use sites).
+__device__ __forceinline__ double min_image(double centre, double x, double L) {
+    double d = centre - x;
+    if (d > 0.5 * L) d -= L;
+    else if (d < -0.5 * L) d += L;
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+template <typename T> void launch_move(const Sim<T>& s, hipStream_t st, int init);
+template <typename T> void launch_geometry(const Sim<T>& s, hipStream_t st, int init);
+template <typename T> void launch_boundary(const Sim<T>& s, hipStream_t st);
+template <typename T> void launch_init_density(const Sim<T>& s, hipStream_t st);
+template <typename T> void launch_charge_poisson(const Sim<T>& s, hipStream_t st);
+template <typename T> void launch_ek(const Sim<T>& s, hipStream_t st);
+template <typename T> void launch_lb(const Sim<T>& s, hipStream_t st);
+template <typename T> void launch_refill(const Sim<T>& s, hipStream_t st);
+template <typename T> void launch_hydro(const Sim<T>& s, hipStream_t st);
+template <typename T> void launch_forces(const Sim<T>& s, hipStream_t st);
+template <typename T> void fill(T* p, long n, T v, hipStream_t st);
+template <typename T> void launch_finish(const Sim<T>& s, hipStream_t st);
+template <typename T> void launch_diagnostics(const Sim<T>& s, hipStream_t st, double* out);
+
+}  // namespace ek

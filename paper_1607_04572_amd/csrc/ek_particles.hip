@@ -1,0 +1,775 @@
+// ek_particles.hip -- particle-local kernels: integration, coverage (flags,
+// owners, partial volumes Psi, particle charge), the moving-boundary update of
+// the LB fluid and the solute, momentum-exchange and electrostatic forces.
+//
+// Work decomposition: one workgroup (or a row of workgroups) per particle,
+// looping over the particle's box: the cells within R + 2 of its old or new
+// centre, which contains every cell whose coverage can change in this step.
+// A cell lying in several boxes is written only by the lowest-index box that
+// contains it, so every kernel here is race-free without atomics, and every
+// per-particle sum is a fixed-order workgroup reduction (deterministic).
+//
+// Coverage decisions (inside/outside a sphere) are taken in FP64 with FMA
+// contraction disabled, in the same operation order as the reference
+// definition, so the boundary sets are bit-identical for identical positions.
+#include "ek_internal.h"
+
+namespace ek {
+
+constexpr int PT = 256;  // threads per particle workgroup
+
+// ---------------------------------------------------------------------------
+// Psi: overlapped volume fraction by recursive subdivision (Sec. III.D.2): a
+// box entirely inside counts fully, entirely outside counts zero, otherwise it
+// is split into 8; at depth 4 an undecided box counts iff its centre is inside.
+// Returned as a count of depth-4 sub-cells (0..4096).
+// ---------------------------------------------------------------------------
+template <int DEPTH>
+__device__ __noinline__ int psi_box(double lx, double ly, double lz, double h, double R2);
+
+template <int DEPTH>
+__device__ __forceinline__ int psi_box_body(double lx, double ly, double lz, double h, double R2) {
+#pragma clang fp contract(off)
+    double hx = lx + h, hy = ly + h, hz = lz + h;
+    double fx = (lx * lx > hx * hx) ? lx * lx : hx * hx;
+    double fy = (ly * ly > hy * hy) ? ly * ly : hy * hy;
+    double fz = (lz * lz > hz * hz) ? lz * lz : hz * hz;
+    double far2 = (fx + fy) + fz;
+    constexpr int leaves = 1 << (3 * (4 - DEPTH));
+    if (far2 <= R2) return leaves;
+    double nx = (lx > 0.0) ? lx : ((hx < 0.0) ? hx : 0.0);
+    double ny = (ly > 0.0) ? ly : ((hy < 0.0) ? hy : 0.0);
+    double nz = (lz > 0.0) ? lz : ((hz < 0.0) ? hz : 0.0);
+    double near2 = (nx * nx + ny * ny) + nz * nz;
+    if (near2 >= R2) return 0;
+    if constexpr (DEPTH == 4) {
+        double cx = lx + 0.5 * h, cy = ly + 0.5 * h, cz = lz + 0.5 * h;
+        return ((cx * cx + cy * cy) + cz * cz) <= R2 ? 1 : 0;
+    } else {
+        double hh = 0.5 * h;
+        int s = 0;
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            int a = (k >> 2) & 1, b = (k >> 1) & 1, c = k & 1;
+            s += psi_box<DEPTH + 1>(a ? lx + hh : lx, b ? ly + hh : ly, c ? lz + hh : lz, hh, R2);
+        }
+        return s;
+    }
+}
+
+template <int DEPTH>
+__device__ __noinline__ int psi_box(double lx, double ly, double lz, double h, double R2) {
+    return psi_box_body<DEPTH>(lx, ly, lz, h, R2);
+}
+
+__device__ __forceinline__ int psi_count(double dx, double dy, double dz, double R) {
+#pragma clang fp contract(off)
+    double R2 = R * R;
+    return psi_box_body<0>(dx - 0.5, dy - 0.5, dz - 0.5, 1.0, R2);
+}
+
+__device__ __forceinline__ bool centre_inside(double dx, double dy, double dz, double R) {
+#pragma clang fp contract(off)
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    return d2 <= R * R;
+}
+
+__device__ __forceinline__ bool far_from(double dx, double dy, double dz, double R) {
+    return fabs(dx) > R + 1.0 || fabs(dy) > R + 1.0 || fabs(dz) > R + 1.0;
+}
+
+__device__ __forceinline__ bool in_box(const PState& q, int x, int y, int z, int nx, int ny, int nz) {
+    return wrapi(x - q.box_lo[0], nx) < q.box_n[0] && wrapi(y - q.box_lo[1], ny) < q.box_n[1] &&
+           wrapi(z - q.box_lo[2], nz) < q.box_n[2];
+}
+
+template <typename T>
+__device__ __forceinline__ void cell_disp(const Sim<T>& s, int x, int y, int z, const PState& q, double d[3]) {
+#pragma clang fp contract(off)
+    d[0] = min_image((double)x + 0.5, q.x[0], (double)s.nx);
+    d[1] = min_image((double)y + 0.5, q.x[1], (double)s.ny);
+    d[2] = min_image((double)z + 0.5, q.x[2], (double)s.nz);
+}
+
+// Box cell t (0 <= t < n0*n1*n2) of particle p -> global coordinates.
+template <typename T>
+__device__ __forceinline__ void box_cell(const Sim<T>& s, const PState& q, int t, int& x, int& y, int& z) {
+    int i = t % q.box_n[0];
+    int j = (t / q.box_n[0]) % q.box_n[1];
+    int k = t / (q.box_n[0] * q.box_n[1]);
+    x = wrapi(q.box_lo[0] + i, s.nx);
+    y = wrapi(q.box_lo[1] + j, s.ny);
+    z = wrapi(q.box_lo[2] + k, s.nz);
+}
+
+template <typename T>
+__device__ __forceinline__ bool box_owner_is(const Sim<T>& s, int p, int x, int y, int z) {
+    for (int q = 0; q < p; ++q)
+        if (in_box(s.parts[q], x, y, z, s.nx, s.ny, s.nz)) return false;
+    return true;
+}
+
+template <typename T>
+__device__ __forceinline__ long cidx(const Sim<T>& s, int x, int y, int z) {
+    return (long)wrapi(x, s.nx) + (long)s.nx * ((long)wrapi(y, s.ny) + (long)s.ny * wrapi(z, s.nz));
+}
+
+__device__ __forceinline__ bool stable(uint8_t fl) { return !(fl & (F_CUR | F_PREV | F_WALL)); }
+__device__ __forceinline__ bool covered(uint8_t fl) { return (fl & F_CUR) && !(fl & (F_PREV | F_WALL)); }
+__device__ __forceinline__ bool vacated(uint8_t fl) { return (fl & F_PREV) && !(fl & (F_CUR | F_WALL)); }
+
+// Deterministic workgroup sum of NV doubles (result valid in thread 0).
+template <int NV>
+__device__ void block_sum(double (&v)[NV]) {
+    __shared__ double part[NV][PT / 64];
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) part[k][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double x = 0.0;
+            for (int w = 0; w < PT / 64; ++w) x += part[k][w];
+            v[k] = x;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Particle move (Sec. III.B) and box of this step.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_move(Sim<T> s, int init) {
+#pragma clang fp contract(off)
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= s.np) return;
+    PState& q = s.parts[p];
+    double L[3] = {(double)s.nx, (double)s.ny, (double)s.nz};
+    double xold[3] = {q.x[0], q.x[1], q.x[2]};
+    double disp[3] = {0.0, 0.0, 0.0};
+    if (!init) {
+        if (q.mode == EK_FIXED) {
+            for (int d = 0; d < 3; ++d) q.v[d] = q.w[d] = 0.0;
+        } else {
+            if (q.mode == EK_FREE) {
+                double I = 0.4 * q.M * q.R * q.R;
+                double a = s.integrator == EK_VELOCITY_VERLET ? 0.5 : 1.0;
+                for (int d = 0; d < 3; ++d) {
+                    q.v[d] += a * q.F[d] / q.M;
+                    q.w[d] += a * q.T[d] / I;
+                }
+            }
+            for (int d = 0; d < 3; ++d) {
+                disp[d] = q.v[d];
+                q.x[d] += q.v[d];
+                if (q.x[d] >= L[d]) q.x[d] -= L[d];
+                else if (q.x[d] < 0.0) q.x[d] += L[d];
+            }
+        }
+    }
+    int n[3] = {s.nx, s.ny, s.nz};
+    for (int d = 0; d < 3; ++d) {
+        double lo = fmin(xold[d], xold[d] + disp[d]), hi = fmax(xold[d], xold[d] + disp[d]);
+        int ilo = (int)floor(lo - q.R) - BOX_MARGIN;
+        int ihi = (int)floor(hi + q.R) + BOX_MARGIN;
+        int cnt = ihi - ilo + 1;
+        if (cnt >= n[d]) {
+            ilo = 0;
+            cnt = n[d];
+        }
+        q.box_lo[d] = ilo;
+        q.box_n[d] = cnt;
+        q.disp[d] = disp[d];
+        q.Fc[d] = q.Tc[d] = 0.0;
+    }
+    for (int k = 0; k < MAXS; ++k) q.pool[k] = 0.0;
+    q.ncov = q.nvac = q.npool = q.nflag = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Coverage of the cells of each box: flag (centre inside, Fig. 1), owner
+// (lowest particle index), Psi = min(1, sum_p Psi_p), particle charge rho_b
+// (Psi mode: sum_p Z_p Psi_p / V_p) plus wall charge.  The previous flag and
+// owner are kept in bit1 / owner_prev for the moving-boundary update.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(PT) void k_geometry(Sim<T> s, int init) {
+#pragma clang fp contract(off)
+    int p = blockIdx.y;
+    const PState& me = s.parts[p];
+    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
+        int x, y, z;
+        box_cell(s, me, t, x, y, z);
+        if (!box_owner_is(s, p, x, y, z)) continue;
+        long c = cidx(s, x, y, z);
+        uint8_t old = s.flag[c];
+        uint8_t wall = old & F_WALL;
+        int cur = wall ? 1 : 0;
+        uint16_t ow = NO_OWNER, pso = NO_OWNER;
+        double psum = 0.0;
+        double qb = s.wall_charge ? s.wall_charge[c] : 0.0;
+        for (int k = 0; k < s.np; ++k) {
+            const PState& q = s.parts[k];
+            if (!in_box(q, x, y, z, s.nx, s.ny, s.nz)) continue;
+            double d[3];
+            cell_disp(s, x, y, z, q, d);
+            if (far_from(d[0], d[1], d[2], q.R)) continue;
+            if (!cur && centre_inside(d[0], d[1], d[2], q.R)) {
+                cur = 1;
+                ow = (uint16_t)k;
+            }
+            int cnt = psi_count(d[0], d[1], d[2], q.R);
+            if (cnt > 0) {
+                psum += (double)cnt / 4096.0;
+                pso = (pso == NO_OWNER) ? (uint16_t)k : MULTI_OWNER;
+                if (s.charge_mode == EK_CHARGE_PSI) qb += q.Z * ((double)cnt / 4096.0) / q.Vp;
+            }
+        }
+        uint8_t prev = init ? (uint8_t)cur : (uint8_t)(old & F_CUR);
+        s.flag[c] = (uint8_t)(wall | (cur ? F_CUR : 0) | (prev ? F_PREV : 0));
+        s.owner_prev[c] = init ? ow : s.owner[c];
+        s.owner[c] = ow;
+        s.psi_owner[c] = pso;
+        s.psi[c] = (float)(psum < 1.0 ? psum : 1.0);
+        s.rhob[c] = (T)qb;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double pop_abs(const Sim<T>& s, const T* f, int i, long c, double wi) {
+    return sizeof(T) == 4 ? wi + (double)f[(long)i * s.N + c] : (double)f[(long)i * s.N + c];
+}
+
+template <typename T>
+__device__ __forceinline__ double rho_abs(const Sim<T>& s, const T* r, int k, long c) {
+    return sizeof(T) == 4 ? s.rho_ref[k] + (double)r[(long)k * s.N + c] : (double)r[(long)k * s.N + c];
+}
+
+// ---------------------------------------------------------------------------
+// LB moving boundaries (Sec. III.B, after Aidun): the fluid of a covered cell
+// is destroyed and its momentum p_f goes to the particle (force p_f/tau,
+// applied at the cell centre); a vacated cell is filled with the equilibrium
+// at the surface velocity and the mean density of its stable-fluid D3Q19
+// neighbours (1 if none), and its momentum is taken from the particle.
+// Also counts the particle's boundary cells (n_b) and collects the solute of
+// covered cells that have no stable-fluid neighbour at all (global pool).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
+#pragma clang fp contract(off)
+    int p = blockIdx.x;
+    PState& me = s.parts[p];
+    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    T* f = s.f[s.cur];
+    const T* rho = s.rho[s.cur];
+    // 0-2 Fc, 3-5 Tc, 6..6+MAXS pool, then counts
+    double acc[6 + MAXS + 5];
+    for (int k = 0; k < 6 + MAXS + 5; ++k) acc[k] = 0.0;
+    for (int t = threadIdx.x; t < ncell; t += PT) {
+        int x, y, z;
+        box_cell(s, me, t, x, y, z);
+        long c = cidx(s, x, y, z);
+        uint8_t fl = s.flag[c];
+        if ((fl & F_CUR) && s.owner[c] == p) acc[6 + MAXS + 3] += 1.0;  // n_b
+        if ((fl & (F_CUR | F_PREV)) && !(fl & F_WALL) && box_owner_is(s, p, x, y, z)) acc[6 + MAXS + 4] += 1.0;
+        if (covered(fl) && s.owner[c] == p) {
+            double pf[3] = {0.0, 0.0, 0.0};
+            sfor<19>([&](auto I) {
+                constexpr int i = I;
+                double fi = pop_abs(s, f, i, c, q19w(i));
+                pf[0] += fi * q19x(i);
+                pf[1] += fi * q19y(i);
+                pf[2] += fi * q19z(i);
+            });
+            double r[3];
+            cell_disp(s, x, y, z, me, r);
+            acc[0] += pf[0];
+            acc[1] += pf[1];
+            acc[2] += pf[2];
+            acc[3] += r[1] * pf[2] - r[2] * pf[1];
+            acc[4] += r[2] * pf[0] - r[0] * pf[2];
+            acc[5] += r[0] * pf[1] - r[1] * pf[0];
+            acc[6 + MAXS] += 1.0;
+            int n27 = 0;
+            for (int a = -1; a <= 1; ++a)
+                for (int b = -1; b <= 1; ++b)
+                    for (int e = -1; e <= 1; ++e)
+                        if ((a | b | e) && stable(s.flag[cidx(s, x + a, y + b, z + e)])) n27++;
+            if (n27 == 0) {
+                acc[6 + MAXS + 2] += 1.0;
+                for (int k = 0; k < s.ns; ++k) acc[6 + k] += rho_abs(s, rho, k, c);
+            }
+        }
+        if (vacated(fl) && s.owner_prev[c] == p) {
+            double sum = 0.0;
+            int nf = 0;
+            sfor<19>([&](auto I) {
+                constexpr int i = I;
+                if constexpr (i > 0) {
+                    long n = cidx(s, x + q19x(i), y + q19y(i), z + q19z(i));
+                    if (stable(s.flag[n])) {
+                        double rn = 0.0;
+                        // density of the neighbour (as a deviation from 1 on the FP32 path)
+                        sfor<19>([&](auto J) { rn += (double)f[(long)J * s.N + n]; });
+                        sum += rn;
+                        nf++;
+                    }
+                }
+            });
+            double base = sizeof(T) == 4 ? 0.0 : 1.0;  // stored density of "no neighbour": 1
+            double rbar = nf > 0 ? sum / nf : base;
+            double r[3];
+            cell_disp(s, x, y, z, me, r);
+            double vb[3] = {me.v[0] + (me.w[1] * r[2] - me.w[2] * r[1]),
+                            me.v[1] + (me.w[2] * r[0] - me.w[0] * r[2]),
+                            me.v[2] + (me.w[0] * r[1] - me.w[1] * r[0])};
+            double usq = vb[0] * vb[0] + vb[1] * vb[1] + vb[2] * vb[2];
+            double pf[3] = {0.0, 0.0, 0.0};
+            sfor<19>([&](auto I) {
+                constexpr int i = I;
+                constexpr double w = q19w(i);
+                double cu = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
+                double feq = w * (rbar + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+                T st = (T)feq;
+                f[(long)i * s.N + c] = st;
+                double back = (double)st;
+                pf[0] += back * q19x(i);
+                pf[1] += back * q19y(i);
+                pf[2] += back * q19z(i);
+            });
+            acc[0] -= pf[0];
+            acc[1] -= pf[1];
+            acc[2] -= pf[2];
+            acc[3] -= r[1] * pf[2] - r[2] * pf[1];
+            acc[4] -= r[2] * pf[0] - r[0] * pf[2];
+            acc[5] -= r[0] * pf[1] - r[1] * pf[0];
+            acc[6 + MAXS + 1] += 1.0;
+        }
+    }
+    block_sum(acc);
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 3; ++d) {
+            me.Fc[d] = acc[d];
+            me.Tc[d] = acc[3 + d];
+        }
+        for (int k = 0; k < MAXS; ++k) me.pool[k] = acc[6 + k];
+        me.ncov = (int)acc[6 + MAXS];
+        me.nvac = (int)acc[6 + MAXS + 1];
+        me.npool = (int)acc[6 + MAXS + 2];
+        me.nb = (int)acc[6 + MAXS + 3];
+        me.nflag = (int)acc[6 + MAXS + 4];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Solute expel (Sec. III.D.1), gather form in FP64: every stable-fluid cell
+// collects, from each covered neighbour c, rho(c)/n19(c) if it is one of c's
+// n19 stable D3Q19 neighbours; if c has no such neighbour, rho(c)/n27(c) from
+// the D3Q27 neighbourhood.  Covered cells are emptied by k_boundary_post.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(PT) void k_expel(Sim<T> s) {
+    int p = blockIdx.y;
+    const PState& me = s.parts[p];
+    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    T* rho = s.rho[s.cur];
+    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
+        int x, y, z;
+        box_cell(s, me, t, x, y, z);
+        long n = cidx(s, x, y, z);
+        if (!stable(s.flag[n])) continue;
+        if (!box_owner_is(s, p, x, y, z)) continue;
+        double gain[MAXS] = {0.0, 0.0, 0.0, 0.0};
+        bool any = false;
+        for (int a = -1; a <= 1; ++a)
+            for (int b = -1; b <= 1; ++b)
+                for (int e = -1; e <= 1; ++e) {
+                    if (!(a | b | e)) continue;
+                    long c = cidx(s, x + a, y + b, z + e);
+                    if (!covered(s.flag[c])) continue;
+                    int cx = x + a, cy = y + b, cz = z + e;
+                    int n19 = 0, n27 = 0;
+                    for (int a2 = -1; a2 <= 1; ++a2)
+                        for (int b2 = -1; b2 <= 1; ++b2)
+                            for (int e2 = -1; e2 <= 1; ++e2) {
+                                if (!(a2 | b2 | e2)) continue;
+                                if (!stable(s.flag[cidx(s, cx + a2, cy + b2, cz + e2)])) continue;
+                                n27++;
+                                if (abs(a2) + abs(b2) + abs(e2) <= 2) n19++;
+                            }
+                    bool is19 = abs(a) + abs(b) + abs(e) <= 2;
+                    int div = 0;
+                    if (n19 > 0) div = is19 ? n19 : 0;
+                    else if (n27 > 0) div = n27;
+                    if (div == 0) continue;
+                    any = true;
+                    for (int k = 0; k < s.ns; ++k) gain[k] += rho_abs(s, rho, k, c) / div;
+                }
+        if (!any) continue;
+        for (int k = 0; k < s.ns; ++k) {
+            double v = rho_abs(s, rho, k, n) + gain[k];
+            rho[(long)k * s.N + n] = (T)(sizeof(T) == 4 ? v - s.rho_ref[k] : v);
+        }
+    }
+}
+
+// Covered cells lose their solute; in the uniform charge mode each owned cell
+// receives Z / n_b of its particle's charge.
+template <typename T>
+__global__ __launch_bounds__(PT) void k_boundary_post(Sim<T> s) {
+    int p = blockIdx.y;
+    const PState& me = s.parts[p];
+    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    T* rho = s.rho[s.cur];
+    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
+        int x, y, z;
+        box_cell(s, me, t, x, y, z);
+        long c = cidx(s, x, y, z);
+        uint8_t fl = s.flag[c];
+        if (!(fl & F_CUR) || s.owner[c] != p) continue;
+        if (covered(fl))
+            for (int k = 0; k < s.ns; ++k) rho[(long)k * s.N + c] = (T)(sizeof(T) == 4 ? -s.rho_ref[k] : 0.0);
+        if (s.charge_mode == EK_CHARGE_UNIFORM && me.nb > 0) {
+            double qb = (s.wall_charge ? s.wall_charge[c] : 0.0) + me.Z / (double)me.nb;
+            s.rhob[c] = (T)qb;
+        }
+    }
+}
+
+// Solute of covered cells with no stable-fluid neighbour in their whole
+// 26-neighbourhood is spread uniformly over all stable-fluid cells.  Exits at
+// once when there is none (the usual case).
+template <typename T>
+__global__ __launch_bounds__(PT) void k_pool(Sim<T> s) {
+    double pool[MAXS] = {0.0, 0.0, 0.0, 0.0};
+    long nflag = 0;
+    bool any = false;
+    for (int q = 0; q < s.np; ++q) {
+        const PState& pq = s.parts[q];
+        if (pq.npool) any = true;
+        for (int k = 0; k < MAXS; ++k) pool[k] += pq.pool[k];
+        nflag += pq.nflag;
+    }
+    if (!any) return;
+    long nS = s.N - s.n_wall - nflag;
+    if (nS <= 0) return;
+    T* rho = s.rho[s.cur];
+    for (long c = (long)blockIdx.x * PT + threadIdx.x; c < s.N; c += (long)gridDim.x * PT) {
+        if (!stable(s.flag[c])) continue;
+        for (int k = 0; k < s.ns; ++k) {
+            double v = rho_abs(s, rho, k, c) + pool[k] / (double)nS;
+            rho[(long)k * s.N + c] = (T)(sizeof(T) == 4 ? v - s.rho_ref[k] : v);
+        }
+    }
+}
+
+// Initial density rule: boundary cells empty; partial-volume fluid cells keep
+// (1 - Psi) of the given concentration.  Whole grid, once.
+template <typename T>
+__global__ __launch_bounds__(PT) void k_init_density(Sim<T> s) {
+    long c = (long)blockIdx.x * PT + threadIdx.x;
+    if (c >= s.N) return;
+    uint8_t fl = s.flag[c];
+    double psi = s.psi[c];
+    for (int k = 0; k < s.ns; ++k) {
+        T* r = s.rho[s.cur] + (long)k * s.N;
+        double v = rho_abs(s, s.rho[s.cur], k, c);
+        if (fl & F_CUR) v = 0.0;
+        else if (s.pv) v *= (1.0 - psi);
+        r[c] = (T)(sizeof(T) == 4 ? v - s.rho_ref[k] : v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forces on the particles.
+// Momentum exchange (Sec. III.B, Eq. force): for each link from a fluid cell
+// x_f to a boundary cell x_b = x_f + c_i owned by p, the reflected population
+// f_i*(x_f) transfers c_i (2 f_i* - 6 w_i rho0 c_i.v_b); torque about the centre.
+// Electrostatic: F = kT sum rho_b,p (E - grad phi), central differences.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(PT) void k_hydro_force(Sim<T> s) {
+#pragma clang fp contract(off)
+    int p = blockIdx.x;
+    PState& me = s.parts[p];
+    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const T* f = s.f[s.cur];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < ncell; t += PT) {
+        int x, y, z;
+        box_cell(s, me, t, x, y, z);
+        long b = cidx(s, x, y, z);
+        if (!(s.flag[b] & F_CUR) || s.owner[b] != p) continue;
+        double r[3];
+        cell_disp(s, x, y, z, me, r);
+        double vb[3] = {me.v[0] + (me.w[1] * r[2] - me.w[2] * r[1]),
+                        me.v[1] + (me.w[2] * r[0] - me.w[0] * r[2]),
+                        me.v[2] + (me.w[0] * r[1] - me.w[1] * r[0])};
+        sfor<19>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) {
+                long xf = cidx(s, x - q19x(i), y - q19y(i), z - q19z(i));
+                if (!(s.flag[xf] & F_CUR)) {
+                    constexpr double w = q19w(i);
+                    double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
+                    double tt = 2.0 * pop_abs(s, f, i, xf, w) - 6.0 * w * cv;
+                    double df[3] = {q19x(i) * tt, q19y(i) * tt, q19z(i) * tt};
+                    acc[0] += df[0];
+                    acc[1] += df[1];
+                    acc[2] += df[2];
+                    acc[3] += r[1] * df[2] - r[2] * df[1];
+                    acc[4] += r[2] * df[0] - r[0] * df[2];
+                    acc[5] += r[0] * df[1] - r[1] * df[0];
+                }
+            }
+        });
+    }
+    block_sum(acc);
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) {
+            me.Fh[d] = acc[d];
+            me.Th[d] = acc[3 + d];
+        }
+}
+
+template <typename T>
+__global__ __launch_bounds__(PT) void k_el_force(Sim<T> s) {
+#pragma clang fp contract(off)
+    int p = blockIdx.x;
+    PState& me = s.parts[p];
+    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < ncell; t += PT) {
+        int x, y, z;
+        box_cell(s, me, t, x, y, z);
+        long c = cidx(s, x, y, z);
+        double qb = 0.0;
+        if (s.charge_mode == EK_CHARGE_UNIFORM) {
+            if (!(s.flag[c] & F_CUR) || s.owner[c] != p || me.nb == 0) continue;
+            qb = me.Z / (double)me.nb;
+        } else {
+            uint16_t po = s.psi_owner[c];
+            double psip;
+            if (po == (uint16_t)p) {
+                psip = (double)s.psi[c];
+            } else if (po == MULTI_OWNER) {
+                double d[3];
+                cell_disp(s, x, y, z, me, d);
+                if (far_from(d[0], d[1], d[2], me.R)) continue;
+                psip = (double)psi_count(d[0], d[1], d[2], me.R) / 4096.0;
+            } else {
+                continue;
+            }
+            if (psip == 0.0) continue;
+            qb = me.Z * psip / me.Vp;
+        }
+        double g[3];
+        g[0] = 0.5 * ((double)s.phi[cidx(s, x + 1, y, z)] - (double)s.phi[cidx(s, x - 1, y, z)]);
+        g[1] = 0.5 * ((double)s.phi[cidx(s, x, y + 1, z)] - (double)s.phi[cidx(s, x, y - 1, z)]);
+        g[2] = 0.5 * ((double)s.phi[cidx(s, x, y, z + 1)] - (double)s.phi[cidx(s, x, y, z - 1)]);
+        double fc[3];
+        for (int e = 0; e < 3; ++e) fc[e] = s.kT * qb * (s.E[e] - g[e]);
+        double d[3];
+        cell_disp(s, x, y, z, me, d);
+        acc[0] += fc[0];
+        acc[1] += fc[1];
+        acc[2] += fc[2];
+        acc[3] += d[1] * fc[2] - d[2] * fc[1];
+        acc[4] += d[2] * fc[0] - d[0] * fc[2];
+        acc[5] += d[0] * fc[1] - d[1] * fc[0];
+    }
+    block_sum(acc);
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) {
+            me.Fe[d] = acc[d];
+            me.Te[d] = acc[3 + d];
+        }
+}
+
+// Total force of the step and the closing half kick of velocity Verlet.
+template <typename T>
+__global__ void k_finish(Sim<T> s) {
+#pragma clang fp contract(off)
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= s.np) return;
+    PState& q = s.parts[p];
+    double Fn[3], Tn[3];
+    for (int d = 0; d < 3; ++d) {
+        Fn[d] = (q.Fh[d] + q.Fe[d]) + q.Fc[d];
+        Tn[d] = (q.Th[d] + q.Te[d]) + q.Tc[d];
+    }
+    if (q.mode == EK_FREE && s.integrator == EK_VELOCITY_VERLET) {
+        double I = 0.4 * q.M * q.R * q.R;
+        for (int d = 0; d < 3; ++d) {
+            q.v[d] += 0.5 * Fn[d] / q.M;
+            q.w[d] += 0.5 * Tn[d] / I;
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        q.F[d] = Fn[d];
+        q.T[d] = Tn[d];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Simple scheme (Sec. III.D.1, Eqs. refill and refill-neighbours): a vacated
+// cell v with N_f stable-fluid D3Q19 neighbours receives
+// sum_n rho(n) / (N_f + 1); each such neighbour n gives rho(n) / (N_f(v) + 1)
+// to every vacated neighbour v (all from the post-expel values: the first
+// kernel writes only vacated cells and reads only stable ones, the second
+// writes only stable cells and reads only their own values and flags).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int stable19(const Sim<T>& s, int x, int y, int z) {
+    int nf = 0;
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i > 0)
+            if (stable(s.flag[cidx(s, x + q19x(i), y + q19y(i), z + q19z(i))])) nf++;
+    });
+    return nf;
+}
+
+template <typename T>
+__global__ __launch_bounds__(PT) void k_refill_vacated(Sim<T> s) {
+    int p = blockIdx.y;
+    const PState& me = s.parts[p];
+    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    T* rho = s.rho[s.cur];
+    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
+        int x, y, z;
+        box_cell(s, me, t, x, y, z);
+        long v = cidx(s, x, y, z);
+        if (!vacated(s.flag[v]) || s.owner_prev[v] != p) continue;
+        int nf = stable19(s, x, y, z);
+        for (int k = 0; k < s.ns; ++k) {
+            double acc = rho_abs(s, rho, k, v);
+            sfor<19>([&](auto I) {
+                constexpr int i = I;
+                if constexpr (i > 0) {
+                    long n = cidx(s, x + q19x(i), y + q19y(i), z + q19z(i));
+                    if (stable(s.flag[n])) acc += rho_abs(s, rho, k, n) / (nf + 1);
+                }
+            });
+            rho[(long)k * s.N + v] = (T)(sizeof(T) == 4 ? acc - s.rho_ref[k] : acc);
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(PT) void k_refill_stable(Sim<T> s) {
+    int p = blockIdx.y;
+    const PState& me = s.parts[p];
+    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    T* rho = s.rho[s.cur];
+    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
+        int x, y, z;
+        box_cell(s, me, t, x, y, z);
+        long n = cidx(s, x, y, z);
+        if (!stable(s.flag[n]) || !box_owner_is(s, p, x, y, z)) continue;
+        double share = 0.0;  // sum over vacated neighbours of 1/(N_f(v)+1)
+        bool any = false;
+        sfor<19>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) {
+                int vx = x + q19x(i), vy = y + q19y(i), vz = z + q19z(i);
+                if (vacated(s.flag[cidx(s, vx, vy, vz)])) {
+                    any = true;
+                    share += 1.0 / (stable19(s, vx, vy, vz) + 1);
+                }
+            }
+        });
+        if (!any) continue;
+        for (int k = 0; k < s.ns; ++k) {
+            double r = rho_abs(s, rho, k, n);
+            double loss = 0.0;
+            sfor<19>([&](auto I) {
+                constexpr int i = I;
+                if constexpr (i > 0) {
+                    int vx = x + q19x(i), vy = y + q19y(i), vz = z + q19z(i);
+                    if (vacated(s.flag[cidx(s, vx, vy, vz)])) loss += r / (stable19(s, vx, vy, vz) + 1);
+                }
+            });
+            double out = r - loss;
+            rho[(long)k * s.N + n] = (T)(sizeof(T) == 4 ? out - s.rho_ref[k] : out);
+        }
+        (void)share;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int box_chunks(int box_max) { return (box_max + PT - 1) / PT < 64 ? (box_max + PT - 1) / PT : 64; }
+
+template <typename T>
+void launch_move(const Sim<T>& s, hipStream_t st, int init) {
+    if (s.np == 0) return;
+    hipLaunchKernelGGL(k_move<T>, dim3((s.np + 63) / 64), dim3(64), 0, st, s, init);
+}
+
+template <typename T>
+void launch_geometry(const Sim<T>& s, hipStream_t st, int init) {
+    if (s.np == 0) return;
+    hipLaunchKernelGGL(k_geometry<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s, init);
+}
+
+template <typename T>
+void launch_boundary(const Sim<T>& s, hipStream_t st) {
+    if (s.np == 0) return;
+    hipLaunchKernelGGL(k_boundary<T>, dim3(s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_expel<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_boundary_post<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_pool<T>, dim3(256), dim3(PT), 0, st, s);
+}
+
+template <typename T>
+void launch_refill(const Sim<T>& s, hipStream_t st) {
+    if (s.np == 0) return;
+    hipLaunchKernelGGL(k_refill_vacated<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_refill_stable<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
+}
+
+template <typename T>
+void launch_init_density(const Sim<T>& s, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_density<T>, dim3((unsigned)((s.N + PT - 1) / PT)), dim3(PT), 0, st, s);
+}
+
+template <typename T>
+void launch_forces(const Sim<T>& s, hipStream_t st) {
+    if (s.np == 0) return;
+    hipLaunchKernelGGL(k_el_force<T>, dim3(s.np), dim3(PT), 0, st, s);
+}
+
+template <typename T>
+void launch_hydro(const Sim<T>& s, hipStream_t st) {
+    if (s.np == 0) return;
+    hipLaunchKernelGGL(k_hydro_force<T>, dim3(s.np), dim3(PT), 0, st, s);
+}
+
+template <typename T>
+void launch_finish(const Sim<T>& s, hipStream_t st) {
+    if (s.np == 0) return;
+    hipLaunchKernelGGL(k_finish<T>, dim3((s.np + 63) / 64), dim3(64), 0, st, s);
+}
+
+#define EK_INST(T)                                                     \
+    template void launch_move<T>(const Sim<T>&, hipStream_t, int);     \
+    template void launch_geometry<T>(const Sim<T>&, hipStream_t, int); \
+    template void launch_boundary<T>(const Sim<T>&, hipStream_t);      \
+    template void launch_init_density<T>(const Sim<T>&, hipStream_t);  \
+    template void launch_refill<T>(const Sim<T>&, hipStream_t);        \
+    template void launch_forces<T>(const Sim<T>&, hipStream_t);        \
+    template void launch_hydro<T>(const Sim<T>&, hipStream_t);         \
+    template void launch_finish<T>(const Sim<T>&, hipStream_t);
+EK_INST(float)
+EK_INST(double)
+
+}  // namespace ek

@@ -1,0 +1,101 @@
+// ek_util.hip -- fills and FP64 global reductions (diagnostics).
+//
+// The diagnostics are deterministic two-stage sums: each workgroup reduces a
+// fixed strided subset of cells in a fixed order, then one workgroup adds the
+// partial sums in workgroup order.
+#include "ek_internal.h"
+
+namespace ek {
+
+constexpr int UT = 256;
+
+template <typename T>
+__global__ void k_fill(T* p, long n, T v) {
+    for (long i = (long)blockIdx.x * UT + threadIdx.x; i < n; i += (long)gridDim.x * UT) p[i] = v;
+}
+
+template <typename T>
+void fill(T* p, long n, T v, hipStream_t st) {
+    if (n <= 0) return;
+    long blocks = (n + UT - 1) / UT;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(UT), 0, st, p, n, v);
+}
+template void fill<float>(float*, long, float, hipStream_t);
+template void fill<double>(double*, long, double, hipStream_t);
+template void fill<uint8_t>(uint8_t*, long, uint8_t, hipStream_t);
+template void fill<uint16_t>(uint16_t*, long, uint16_t, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(UT) void k_diag_stage1(Sim<T> s) {
+    constexpr bool DEV = sizeof(T) == 4;
+    double acc[NDIAG];
+    for (int k = 0; k < NDIAG; ++k) acc[k] = 0.0;
+    const T* f = s.f[s.cur];
+    const T* rho = s.rho[s.cur];
+    for (long c = (long)blockIdx.x * UT + threadIdx.x; c < s.N; c += (long)gridDim.x * UT) {
+        for (int k = 0; k < s.ns; ++k)
+            acc[k] += (DEV ? s.rho_ref[k] : 0.0) + (double)rho[(long)k * s.N + c];
+        acc[MAXS] += (double)s.rhob[c];
+        if (s.flag[c] & F_CUR) {
+            acc[MAXS + 5] += 1.0;
+            continue;
+        }
+        double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        sfor<19>([&](auto I) {
+            constexpr int i = I;
+            double fi = (DEV ? q19w(i) : 0.0) + (double)f[(long)i * s.N + c];
+            m += fi;
+            jx += fi * q19x(i);
+            jy += fi * q19y(i);
+            jz += fi * q19z(i);
+        });
+        acc[MAXS + 1] += m;
+        acc[MAXS + 2] += jx;
+        acc[MAXS + 3] += jy;
+        acc[MAXS + 4] += jz;
+        double ux = s.u[c], uy = s.u[s.N + c], uz = s.u[2 * s.N + c];
+        double um = sqrt(ux * ux + uy * uy + uz * uz);
+        acc[MAXS + 6] = um > acc[MAXS + 6] ? um : acc[MAXS + 6];
+    }
+    __shared__ double part[NDIAG][UT / 64];
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < NDIAG; ++k) {
+        double x = acc[k];
+        for (int off = 32; off > 0; off >>= 1) {
+            double y = __shfl_xor(x, off);
+            x = (k == MAXS + 6) ? (y > x ? y : x) : x + y;
+        }
+        if (lane == 0) part[k][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < NDIAG) {
+        int k = threadIdx.x;
+        double x = part[k][0];
+        for (int w = 1; w < UT / 64; ++w) x = (k == MAXS + 6) ? (part[k][w] > x ? part[k][w] : x) : x + part[k][w];
+        s.scratch[(long)blockIdx.x * NDIAG + k] = x;
+    }
+}
+
+__global__ void k_diag_stage2(const double* part, int nblocks, double* out) {
+    int k = threadIdx.x;
+    if (k >= NDIAG) return;
+    double x = part[k];
+    for (int b = 1; b < nblocks; ++b) {
+        double y = part[(long)b * NDIAG + k];
+        x = (k == MAXS + 6) ? (y > x ? y : x) : x + y;
+    }
+    out[k] = x;
+}
+
+template <typename T>
+void launch_diagnostics(const Sim<T>& s, hipStream_t st, double* out) {
+    long blocks = (s.N + UT - 1) / UT;
+    if (blocks > DIAG_BLOCKS) blocks = DIAG_BLOCKS;
+    hipLaunchKernelGGL(k_diag_stage1<T>, dim3((unsigned)blocks), dim3(UT), 0, st, s);
+    hipLaunchKernelGGL(k_diag_stage2, dim3(1), dim3(64), 0, st, (const double*)s.scratch, (int)blocks, out);
+}
+template void launch_diagnostics<float>(const Sim<float>&, hipStream_t, double*);
+template void launch_diagnostics<double>(const Sim<double>&, hipStream_t, double*);
+
+}  // namespace ek
