@@ -1,0 +1,189 @@
+#!/usr/bin/env python
+"""Throughput of the full coupled step (EK + LB + moving charged spheres) on one
+MI355X, in million lattice-cell updates per second (MLUPS).
+
+Default workload: 256^3 periodic box (16.8 M cells), FP32 storage with
+deviations, 64 free charged spheres (R = 6, Z = +40), two monovalent species at
+0.01, E = 0.01 along x -- the size at which the working set (~3.6 GB) exceeds
+the 256 MB Infinity Cache, so that bandwidths are HBM bandwidths.  The same
+workload is also timed in FP64 plain storage and the FP32/FP64 speedup
+reported.  Inputs are seeded and synthetic (workloads.py) and resident in HBM
+before the timed region.
+
+One JSON line is printed with the contract fields plus:
+  roofline      -- the dominant kernel (LB stream/collide): algorithmic bytes
+                   per launch / its mean duration from HIP events on the
+                   library's stream, against the 8 TB/s HBM peak;
+  cpu_baseline  -- the FP64 CPU oracle timed on one step of the same workload;
+  kernels       -- per-stage mean times and algorithmic-byte bandwidths;
+  fp64_plain    -- the same workload in FP64.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "EK MLUPS + % HBM roofline, FP32 vs FP64 plain; p50/p99 latency in serve loop"
+
+
+def algorithmic_bytes(stage: str, w, elem: int) -> float:
+    """Minimal HBM bytes per cell of one launch of a stage's kernels."""
+    ns = len(w.species)
+    nx = w.shape[0]
+    h = (nx // 2 + 1) / nx  # half-spectrum cells per real cell
+    cpx = 2 * elem
+    if stage == "lb":
+        # read and write 19 populations, read the force density, write the velocity, read the flag
+        return 19 * elem * 2 + 3 * elem + 3 * elem + 1
+    if stage == "ek":
+        # read densities, potential, Psi (float), velocity, flag; write densities and force
+        return ns * elem + elem + 4 + 3 * elem + 1 + ns * elem + 3 * elem
+    if stage == "poisson":
+        # X: read densities + particle charge, write half spectrum; Y, Z(+inverse), Y':
+        # read + write it; X': read it, write phi
+        return (ns * elem + elem + h * cpx) + 3 * 2 * h * cpx + (h * cpx + elem)
+    return 0.0
+
+
+def run_gpu(w, steps: int, warmup: int, profile_steps: int):
+    import numpy as np  # noqa: F401
+    import torch
+
+    from paper_1607_04572_amd import workloads as W
+    from paper_1607_04572_amd.ek import EkSim
+
+    rho0 = W.initial_densities(w)
+    sim = EkSim(w, initial_density=rho0)
+    sim.prepare()
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = sim.profile(profile_steps)
+    diag = sim.diagnostics()
+    sim.close()
+    del sim
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return dt, stages, diag
+
+
+def copy_probe(mib: int, reps: int = 10) -> dict:
+    """Plain device copy of `mib` MiB (the library's copy kernel), timed with
+    HIP events: the achievable streaming bandwidth, and a kernel of known
+    traffic (mib MiB read + mib MiB written per launch) for scaling counters."""
+    import torch
+
+    from paper_1607_04572_amd.ek import ek_copy_probe
+    n = mib * (1 << 20)
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    st = torch.cuda.current_stream()
+    ek_copy_probe(b.data_ptr(), a.data_ptr(), n, st.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        ek_copy_probe(b.data_ptr(), a.data_ptr(), n, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_per_launch": 2 * n, "ms": ms, "GBps": 2 * n / (ms * 1e-3) / 1e9}
+
+
+def cpu_baseline(w) -> dict:
+    """The FP64 CPU oracle on one full step of the same workload."""
+    import ctypes
+
+    from oracle import oracle as O
+    from paper_1607_04572_amd import workloads as W
+
+    p = O.make_params(*w.shape, w.nu, w.kT, w.lambda_B, w.E, [(s.D, s.z) for s in w.species],
+                      partial_volume=w.scheme == "pv", charge_mode=1 if w.charge == "uniform" else 0,
+                      integrator=0 if w.integrator == "vv" else 1)
+    spheres = [dict(x=s.x, R=s.R, Z=s.Z, M=s.M, v=s.v, mode=s.mode) for s in w.spheres]
+    o = O.OracleSim(p, spheres, W.initial_densities(w))
+    t0 = time.perf_counter()
+    o.step()
+    dt = time.perf_counter() - t0
+    lib = O.lib()
+    lib.or_num_threads.restype = ctypes.c_int
+    threads = int(lib.or_num_threads())
+    return {"value": w.cells / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"1 full step of {w.name} ({w.cells} cells, FP64 oracle), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run the plain copy kernel on buffers of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU "
+              "path: the domain decomposition is a design note, not an implementation.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1607_04572_amd import workloads as W
+
+    w32 = W.CONFIGS[args.workload]("fp32") if args.workload != "c0" else W.c0()
+    dt, stages, diag = run_gpu(w32, args.steps, args.warmup, args.profile_steps)
+    mlups = w32.cells * args.steps / dt / 1e6
+    kern = {}
+    for st in ("lb", "ek", "poisson"):
+        b = algorithmic_bytes(st, w32, 4) * w32.cells
+        ms = stages[st]
+        kern[st] = {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9, "bytes_per_cell": algorithmic_bytes(st, w32, 4)}
+    lb = kern["lb"]
+    out = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": w32.name, "cells": w32.cells, "shape": list(w32.shape),
+                   "spheres": len(w32.spheres), "species": len(w32.species),
+                   "storage": "fp32 deviations (fp64 particles, sums, redistribution)",
+                   "scheme": "partial volume", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_lb (stream/collide)", "achieved": lb["GBps"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": lb["GBps"] / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": lb["bytes_per_cell"] * w32.cells,
+                     "launch_ms": lb["ms"]},
+        "kernels": {"stage_ms": stages, **{k: v for k, v in kern.items()}},
+        "diagnostics": {"species_total": [float(x) for x in diag["species_total"][:len(w32.species)]],
+                        "max_velocity": diag["max_velocity"]},
+    }
+    if not args.no_fp64:
+        w64 = w32.replace(precision="fp64", name=w32.name.replace("fp32", "fp64"))
+        steps64 = max(10, args.steps // 2)
+        dt64, st64, _ = run_gpu(w64, steps64, args.warmup, args.profile_steps)
+        m64 = w64.cells * steps64 / dt64 / 1e6
+        b64 = algorithmic_bytes("lb", w64, 8) * w64.cells
+        out["fp64_plain"] = {"value": m64, "unit": "MLUPS", "ms_per_step": dt64 / steps64 * 1e3,
+                             "steps": steps64, "stage_ms": st64,
+                             "lb_GBps": b64 / (st64["lb"] * 1e-3) / 1e9}
+        out["fp32_over_fp64"] = mlups / m64
+    if args.copy_probe_mib:
+        out["copy_probe"] = copy_probe(args.copy_probe_mib)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w32)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -192,6 +192,27 @@ int ek_get_diagnostics(ek_ctx* c, ek_diag* out);
 int ek_get_state(ek_ctx* c, void* host, size_t* bytes);
 int ek_set_state(ek_ctx* c, const void* host, size_t bytes);
 
+/* Instrumentation: run n steps without graph replay, timing each stage with
+ * HIP events recorded on the context's stream.  ms_out[k] (k < n_out <=
+ * EK_N_STAGES) receives the mean duration in milliseconds of stage k.  The
+ * steps are real steps of the simulation.  Synchronises. */
+#define EK_STAGE_MOVE 0      /* particle kick/drift and boxes */
+#define EK_STAGE_GEOMETRY 1  /* flags, owners, Psi, particle charge */
+#define EK_STAGE_BOUNDARY 2  /* Aidun destroy/create, expel, refill, pool */
+#define EK_STAGE_POISSON 3   /* charge assembly + 5 FFT passes */
+#define EK_STAGE_EK 4        /* link fluxes, continuity, coupling force */
+#define EK_STAGE_HYDRO 5     /* momentum-exchange force */
+#define EK_STAGE_LB 6        /* stream/collide */
+#define EK_STAGE_FORCES 7    /* electrostatic force */
+#define EK_STAGE_FINISH 8    /* closing kick */
+#define EK_N_STAGES 9
+int ek_profile_stages(ek_ctx* c, int n, double* ms_out, int n_out);
+
+/* Bandwidth probe: a plain device-to-device copy kernel of `bytes` (a
+ * multiple of 16) on `stream` (hipStream_t; NULL = default stream).  dst and
+ * src are device pointers owned by the caller; the call only enqueues. */
+int ek_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
+
 /* Wait for all enqueued work of the context. */
 int ek_synchronize(ek_ctx* c);
 

@@ -19,8 +19,12 @@
 #include "ek_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 /* ---------------------------------------------------------------------------
  * D3Q19 velocity set (Sec. III.A: rest vector, 6 face and 12 edge neighbours).

@@ -75,6 +75,7 @@ void or_el_force(const or_params* p, const or_particle* pt, int np,
                  const double* phi, const uint8_t* flag, const int32_t* owner,
                  double* F, double* T);
 
+int or_num_threads(void);
 void or_move(const or_params* p, or_particle* pt, int np);
 void or_finish(const or_params* p, or_particle* pt, int np,
                const double* Fnew, const double* Tnew);

@@ -255,6 +255,56 @@ void enqueue_step(const ek_ctx* c, Sim<T> s) {
     launch_finish(s, st);
 }
 
+// One step with a HIP event recorded after each stage (instrumentation).
+template <typename T>
+void enqueue_step_timed(const ek_ctx* c, Sim<T> s, hipEvent_t* ev) {
+    hipStream_t st = c->stream;
+    (void)hipEventRecord(ev[0], st);
+    launch_move(s, st, 0);
+    (void)hipEventRecord(ev[1], st);
+    launch_geometry(s, st, 0);
+    (void)hipEventRecord(ev[2], st);
+    launch_boundary(s, st);
+    if (!s.pv) launch_refill(s, st);
+    (void)hipEventRecord(ev[3], st);
+    launch_charge_poisson(s, st);
+    (void)hipEventRecord(ev[4], st);
+    launch_ek(s, st);
+    (void)hipEventRecord(ev[5], st);
+    launch_hydro(s, st);
+    (void)hipEventRecord(ev[6], st);
+    launch_lb(s, st);
+    (void)hipEventRecord(ev[7], st);
+    launch_forces(s, st);
+    (void)hipEventRecord(ev[8], st);
+    launch_finish(s, st);
+    (void)hipEventRecord(ev[9], st);
+}
+
+template <typename T>
+int profile_steps(ek_ctx* c, Sim<T>& s, int n, double* acc) {
+    hipEvent_t ev[EK_N_STAGES + 1];
+    for (int k = 0; k <= EK_N_STAGES; ++k) HIPCHK(c, hipEventCreate(&ev[k]));
+    int r = EK_OK;
+    for (int i = 0; i < n && r == EK_OK; ++i) {
+        enqueue_step_timed(c, s, ev);
+        if (hipGetLastError() != hipSuccess || hipEventSynchronize(ev[EK_N_STAGES]) != hipSuccess) {
+            c->err = r = EK_ERR_DEVICE;
+            break;
+        }
+        for (int k = 0; k < EK_N_STAGES; ++k) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            acc[k] += ms;
+        }
+        s.cur ^= 1;
+        c->set_cur(s.cur);
+        c->step += 1;
+    }
+    for (int k = 0; k <= EK_N_STAGES; ++k) (void)hipEventDestroy(ev[k]);
+    return r;
+}
+
 template <typename T>
 int build_graph(ek_ctx* c, Sim<T> s, int parity, int nsteps, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
@@ -668,6 +718,27 @@ int ek_step(ek_ctx* c, int n) {
         if (r) return r;
     }
     return c->fp32 ? run_steps(c, c->sf, n) : run_steps(c, c->sd, n);
+}
+
+int ek_profile_stages(ek_ctx* c, int n, double* ms_out, int n_out) {
+    if (!c || n <= 0 || !ms_out || n_out < 1 || n_out > EK_N_STAGES) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    if (!c->prepared) {
+        int r = ek_prepare(c);
+        if (r) return r;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double acc[EK_N_STAGES] = {0};
+    int r = c->fp32 ? profile_steps(c, c->sf, n, acc) : profile_steps(c, c->sd, n, acc);
+    if (r) return r;
+    for (int k = 0; k < n_out; ++k) ms_out[k] = acc[k] / n;
+    return EK_OK;
+}
+
+int ek_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || bytes % 16) return EK_ERR_INVALID_ARG;
+    launch_copy16(dst, src, (long)(bytes / 16), (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? EK_OK : EK_ERR_DEVICE;
 }
 
 int ek_synchronize(ek_ctx* c) {

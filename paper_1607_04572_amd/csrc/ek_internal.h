@@ -152,5 +152,6 @@ template <typename T> void launch_forces(const Sim<T>& s, hipStream_t st);
 template <typename T> void fill(T* p, long n, T v, hipStream_t st);
 template <typename T> void launch_finish(const Sim<T>& s, hipStream_t st);
 template <typename T> void launch_diagnostics(const Sim<T>& s, hipStream_t st, double* out);
+void launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
 
 }  // namespace ek

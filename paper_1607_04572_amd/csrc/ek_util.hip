@@ -98,4 +98,15 @@ void launch_diagnostics(const Sim<T>& s, hipStream_t st, double* out) {
 template void launch_diagnostics<float>(const Sim<float>&, hipStream_t, double*);
 template void launch_diagnostics<double>(const Sim<double>&, hipStream_t, double*);
 
+// Plain streaming copy, 16 bytes per lane per iteration (bandwidth probe).
+__global__ __launch_bounds__(UT) void k_copy16(float4* __restrict__ dst, const float4* __restrict__ src, long n) {
+    for (long i = (long)blockIdx.x * UT + threadIdx.x; i < n; i += (long)gridDim.x * UT) dst[i] = src[i];
+}
+
+void launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
+    long blocks = (n16 + UT - 1) / UT;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(UT), 0, st, (float4*)dst, (const float4*)src, n16);
+}
+
 }  // namespace ek

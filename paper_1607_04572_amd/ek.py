@@ -70,7 +70,9 @@ class ek_diag(C.Structure):
 # ABI symbols declared in include/ek.h
 SYMBOLS = ["ek_query_footprint", "ek_create", "ek_add_sphere", "ek_set_static_boundary", "ek_set_fields",
            "ek_prepare", "ek_step", "ek_get_fields", "ek_get_particles", "ek_get_diagnostics",
-           "ek_get_state", "ek_set_state", "ek_synchronize", "ek_destroy", "ek_strerror"]
+           "ek_get_state", "ek_set_state", "ek_profile_stages", "ek_copy_probe", "ek_synchronize",
+           "ek_destroy", "ek_strerror"]
+STAGES = ["move", "geometry", "boundary", "poisson", "ek", "hydro", "lb", "forces", "finish"]
 
 _LIB = None
 
@@ -98,6 +100,8 @@ def lib():
         L.ek_get_diagnostics.argtypes = [vp, P(ek_diag)]
         L.ek_get_state.argtypes = [vp, vp, P(C.c_size_t)]
         L.ek_set_state.argtypes = [vp, vp, C.c_size_t]
+        L.ek_profile_stages.argtypes = [vp, C.c_int, P(C.c_double), C.c_int]
+        L.ek_copy_probe.argtypes = [vp, vp, C.c_size_t, vp]
         L.ek_synchronize.argtypes = [vp]
         L.ek_destroy.argtypes = [vp]
         L.ek_strerror.argtypes = [C.c_int]
@@ -204,6 +208,17 @@ def ek_set_state(ctx, image: bytes):
     _check(lib().ek_set_state(ctx, C.cast(buf, C.c_void_p), len(image)), "ek_set_state")
 
 
+def ek_profile_stages(ctx, n: int) -> dict:
+    out = (C.c_double * len(STAGES))()
+    _check(lib().ek_profile_stages(ctx, int(n), out, len(STAGES)), "ek_profile_stages")
+    return {k: float(out[i]) for i, k in enumerate(STAGES)}
+
+
+def ek_copy_probe(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int = 0):
+    _check(lib().ek_copy_probe(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), nbytes, C.c_void_p(stream_ptr)),
+           "ek_copy_probe")
+
+
 def ek_synchronize(ctx):
     _check(lib().ek_synchronize(ctx), "ek_synchronize")
 
@@ -277,6 +292,9 @@ class EkSim:
 
     def sync(self):
         ek_synchronize(self.ctx)
+
+    def profile(self, n: int) -> dict:
+        return ek_profile_stages(self.ctx, n)
 
     def field(self, name: str) -> np.ndarray:
         return ek_get_fields(self.ctx, name, self.N, self.ns)
