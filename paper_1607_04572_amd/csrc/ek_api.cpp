@@ -37,7 +37,7 @@ double d_max() {
 
 struct Layout {
     size_t f, rho, u, fext, phi, rhob, psi, flag, owner, owner_prev, psi_owner, spec, tw, k2, parts, scratch,
-        diag, state_end, total;
+        partial, diag, state_end, total;
 };
 
 Layout make_layout(const ek_params* p, size_t ts) {
@@ -67,6 +67,7 @@ Layout make_layout(const ek_params* p, size_t ts) {
     L.tw = take((size_t)(p->nx + p->ny + p->nz) * 2 * ts);
     L.k2 = take((size_t)(p->nx + p->ny + p->nz) * ts);
     L.scratch = take((size_t)DIAG_BLOCKS * NDIAG * sizeof(double));
+    L.partial = take((size_t)PART_KINDS * mp * MAX_CHUNKS * PSTRIDE * sizeof(double));
     L.diag = take(64 * sizeof(double));
     L.total = off;
     return L;
@@ -198,7 +199,9 @@ void setup_sim(ek_ctx* c, Sim<T>& s) {
     s.k2[2] = k2 + p->nx + p->ny;
     s.parts = (PState*)(A + L.parts);
     s.scratch = (double*)(A + L.scratch);
+    s.partial = (double*)(A + L.partial);
     s.box_max = 0;
+    s.nchunk = 1;
     (void)ts;
 }
 
@@ -363,6 +366,8 @@ int prepare(ek_ctx* c, Sim<T>& s) {
     }
     c->sf.np = c->sd.np = np;
     c->sf.box_max = c->sd.box_max = box_max;
+    int nch = (box_max + 255) / 256;
+    c->sf.nchunk = c->sd.nchunk = nch < 1 ? 1 : (nch > MAX_CHUNKS ? MAX_CHUNKS : nch);
     if (np > 0)
         HIPCHK(c, hipMemcpyAsync(s.parts, c->parts.data(), np * sizeof(PState), hipMemcpyHostToDevice, st));
     Sim<T> t = s;
@@ -854,6 +859,8 @@ int ek_set_state(ek_ctx* c, const void* host, size_t bytes) {
         }
         c->sf.np = c->sd.np = np;
         c->sf.box_max = c->sd.box_max = box_max;
+        int nch = (box_max + 255) / 256;
+        c->sf.nchunk = c->sd.nchunk = nch < 1 ? 1 : (nch > MAX_CHUNKS ? MAX_CHUNKS : nch);
         c->prepared = true;
     }
     return EK_OK;

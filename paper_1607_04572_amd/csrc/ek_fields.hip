@@ -234,37 +234,49 @@ __global__ __launch_bounds__(BT) void k_lb(Sim<T> s) {
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    // Pull every population from its source r - c_i first (independent loads),
+    // then replace those whose source is a boundary cell (rare).
     T fi[19];
+    long src[19];
     sfor<19>([&](auto I) {
         constexpr int i = I;
-        // source cell r - c_i
         const int sx = q19x(i) > 0 ? xm : (q19x(i) < 0 ? xp : x);
         const int sy = q19y(i) > 0 ? ym : (q19y(i) < 0 ? yp : y);
         const int sz = q19z(i) > 0 ? zm : (q19z(i) < 0 ? zp : z);
-        const long src = cidx3(s, sx, sy, sz);
-        if constexpr (i == 0) {
-            fi[0] = fs[c];
-        } else {
-            if (s.flag[src] & F_CUR) {
-                // moving bounce-back from the boundary cell src
-                double vb[3] = {0.0, 0.0, 0.0};
-                uint16_t ow = s.owner[src];
-                if (ow != NO_OWNER) {
-                    const PState& q = s.parts[ow];
-                    double r[3] = {min_image((double)sx + 0.5, q.x[0], (double)nx),
-                                   min_image((double)sy + 0.5, q.x[1], (double)ny),
-                                   min_image((double)sz + 0.5, q.x[2], (double)nz)};
-                    vb[0] = q.v[0] + (q.w[1] * r[2] - q.w[2] * r[1]);
-                    vb[1] = q.v[1] + (q.w[2] * r[0] - q.w[0] * r[2]);
-                    vb[2] = q.v[2] + (q.w[0] * r[1] - q.w[1] * r[0]);
-                }
-                double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
-                fi[i] = fs[(long)q19opp(i) * s.N + c] + (T)(6.0 * q19w(i) * cv);
-            } else {
-                fi[i] = fs[(long)i * s.N + src];
-            }
-        }
+        src[i] = cidx3(s, sx, sy, sz);
+        fi[i] = fs[(long)i * s.N + src[i]];
     });
+    const T fx = s.fext[c], fy = s.fext[s.N + c], fz = s.fext[2 * s.N + c];
+    unsigned bmask = 0;
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i > 0) bmask |= (unsigned)(s.flag[src[i]] & F_CUR) << i;
+    });
+    if (bmask) {
+        sfor<19>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) {
+                if (bmask & (1u << i)) {
+                    // moving bounce-back from the boundary cell src
+                    const long b = src[i];
+                    double vb[3] = {0.0, 0.0, 0.0};
+                    uint16_t ow = s.owner[b];
+                    if (ow != NO_OWNER) {
+                        const PState& q = s.parts[ow];
+                        const int bx = (int)(b % nx), by = (int)((b / nx) % ny), bz = (int)(b / ((long)nx * ny));
+                        double r[3] = {min_image((double)bx + 0.5, q.x[0], (double)nx),
+                                       min_image((double)by + 0.5, q.x[1], (double)ny),
+                                       min_image((double)bz + 0.5, q.x[2], (double)nz)};
+                        vb[0] = q.v[0] + (q.w[1] * r[2] - q.w[2] * r[1]);
+                        vb[1] = q.v[1] + (q.w[2] * r[0] - q.w[0] * r[2]);
+                        vb[2] = q.v[2] + (q.w[0] * r[1] - q.w[1] * r[0]);
+                    }
+                    double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
+                    fi[i] = fs[(long)q19opp(i) * s.N + c] + (T)(6.0 * q19w(i) * cv);
+                }
+            }
+        });
+    }
     T rho = (T)0, jx = (T)0, jy = (T)0, jz = (T)0;
     sfor<19>([&](auto I) {
         constexpr int i = I;
@@ -273,7 +285,6 @@ __global__ __launch_bounds__(BT) void k_lb(Sim<T> s) {
         if constexpr (q19y(i) != 0) jy += (T)q19y(i) * fi[i];
         if constexpr (q19z(i) != 0) jz += (T)q19z(i) * fi[i];
     });
-    const T fx = s.fext[c], fy = s.fext[s.N + c], fz = s.fext[2 * s.N + c];
     const T ux = jx + (T)0.5 * fx, uy = jy + (T)0.5 * fy, uz = jz + (T)0.5 * fz;
     const T usq = ux * ux + uy * uy + uz * uz;
     const T uf = ux * fx + uy * fy + uz * fz;
@@ -291,11 +302,11 @@ __global__ __launch_bounds__(BT) void k_lb(Sim<T> s) {
         const T fp = (T)0.5 * (fi[i] + fi[o]);
         const T fm = (T)0.5 * (fi[i] - fi[o]);
         const T delta = (T)3 * w * (cf + (T)1.5 * (g2 * cu * cf - g2 * uf / (T)3));
-        fd[(long)i * s.N + c] = fi[i] + le * (fp - feq_e) + lo * (fm - feq_o) + delta;
+        __builtin_nontemporal_store(fi[i] + le * (fp - feq_e) + lo * (fm - feq_o) + delta, &fd[(long)i * s.N + c]);
     });
-    s.u[c] = ux;
-    s.u[s.N + c] = uy;
-    s.u[2 * s.N + c] = uz;
+    __builtin_nontemporal_store(ux, &s.u[c]);
+    __builtin_nontemporal_store(uy, &s.u[s.N + c]);
+    __builtin_nontemporal_store(uz, &s.u[2 * s.N + c]);
 }
 
 // ---------------------------------------------------------------------------

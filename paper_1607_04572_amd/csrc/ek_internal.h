@@ -27,6 +27,9 @@ constexpr int BOX_MARGIN = 2;
 constexpr int MAX_FFT = 512;
 constexpr int NDIAG = MAXS + 7;       // species totals, rho_b, fluid mass, momentum(3), boundary cells, max|u|
 constexpr int DIAG_BLOCKS = 1024;
+constexpr int MAX_CHUNKS = 32;        // workgroups per particle box
+constexpr int PSTRIDE = 16;           // doubles per partial-sum record
+enum { PART_BOUNDARY = 0, PART_HYDRO = 1, PART_EL = 2, PART_KINDS = 3 };
 
 // ---------------------------------------------------------------------------
 // Compile-time loops and lattice tables
@@ -119,7 +122,9 @@ struct Sim {
     T* k2[3];                 // 2 - 2 cos(2 pi m / n) per axis
     PState* parts;
     double* scratch;          // reductions
+    double* partial;          // per-(particle, chunk) partial sums of the particle kernels
     int box_max;              // bound on cells of one particle box
+    int nchunk;               // workgroups per particle box in the particle kernels
 };
 
 __device__ __forceinline__ int wrapi(int i, int n) {

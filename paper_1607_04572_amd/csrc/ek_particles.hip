@@ -19,53 +19,88 @@ namespace ek {
 constexpr int PT = 256;  // threads per particle workgroup
 
 // ---------------------------------------------------------------------------
-// Psi: overlapped volume fraction by recursive subdivision (Sec. III.D.2): a
-// box entirely inside counts fully, entirely outside counts zero, otherwise it
-// is split into 8; at depth 4 an undecided box counts iff its centre is inside.
-// Returned as a count of depth-4 sub-cells (0..4096).
+// Psi: overlapped volume fraction (Sec. III.D.2), defined by recursive
+// subdivision: a box entirely inside counts fully, entirely outside counts
+// zero, otherwise it is split into 8, down to depth 4 (edge 1/16), where an
+// undecided box counts iff its centre is inside.  Result: a count of depth-4
+// sub-cells (0..4096).
+//
+// Every sub-box corner and leaf centre is (d - 1/2) plus a multiple of 1/32,
+// which FP64 represents exactly, so the recursion's result equals exactly the
+// number of the 4096 leaf centres c with fl(fl(cx^2 + cy^2) + cz^2) <= R^2:
+// a box decided inside has far-corner squares that bound its leaves' squares
+// (rounding is monotone), and a box decided outside has leaves whose squared
+// distance exceeds its near-point bound by at least 1/1024, far beyond
+// rounding.  The GPU therefore classifies the whole cell first and, for cells
+// cut by the surface, counts leaf centres with a full wavefront: lane l takes
+// the leaf columns (i, j) = l, l+64, l+128, l+192 of the 16 x 16 grid.
 // ---------------------------------------------------------------------------
-template <int DEPTH>
-__device__ __noinline__ int psi_box(double lx, double ly, double lz, double h, double R2);
-
-template <int DEPTH>
-__device__ __forceinline__ int psi_box_body(double lx, double ly, double lz, double h, double R2) {
+// Level-0 classification: 4096 (inside), 0 (outside) or -1 (cut by the surface).
+__device__ __forceinline__ int psi_cell_class(double lx, double ly, double lz, double R2) {
 #pragma clang fp contract(off)
-    double hx = lx + h, hy = ly + h, hz = lz + h;
+    double hx = lx + 1.0, hy = ly + 1.0, hz = lz + 1.0;
     double fx = (lx * lx > hx * hx) ? lx * lx : hx * hx;
     double fy = (ly * ly > hy * hy) ? ly * ly : hy * hy;
     double fz = (lz * lz > hz * hz) ? lz * lz : hz * hz;
-    double far2 = (fx + fy) + fz;
-    constexpr int leaves = 1 << (3 * (4 - DEPTH));
-    if (far2 <= R2) return leaves;
+    if ((fx + fy) + fz <= R2) return 4096;
     double nx = (lx > 0.0) ? lx : ((hx < 0.0) ? hx : 0.0);
     double ny = (ly > 0.0) ? ly : ((hy < 0.0) ? hy : 0.0);
     double nz = (lz > 0.0) ? lz : ((hz < 0.0) ? hz : 0.0);
-    double near2 = (nx * nx + ny * ny) + nz * nz;
-    if (near2 >= R2) return 0;
-    if constexpr (DEPTH == 4) {
-        double cx = lx + 0.5 * h, cy = ly + 0.5 * h, cz = lz + 0.5 * h;
-        return ((cx * cx + cy * cy) + cz * cz) <= R2 ? 1 : 0;
-    } else {
-        double hh = 0.5 * h;
-        int s = 0;
-#pragma unroll 1
-        for (int k = 0; k < 8; ++k) {
-            int a = (k >> 2) & 1, b = (k >> 1) & 1, c = k & 1;
-            s += psi_box<DEPTH + 1>(a ? lx + hh : lx, b ? ly + hh : ly, c ? lz + hh : lz, hh, R2);
-        }
-        return s;
-    }
+    if ((nx * nx + ny * ny) + nz * nz >= R2) return 0;
+    return -1;
 }
 
-template <int DEPTH>
-__device__ __noinline__ int psi_box(double lx, double ly, double lz, double h, double R2) {
-    return psi_box_body<DEPTH>(lx, ly, lz, h, R2);
-}
-
-__device__ __forceinline__ int psi_count(double dx, double dy, double dz, double R) {
+// Leaf-centre count of one cut cell, computed by the whole wavefront (all 64
+// lanes must call it with the same arguments).
+__device__ __forceinline__ int wave_leaf_count(double lx, double ly, double lz, double R2) {
 #pragma clang fp contract(off)
-    double R2 = R * R;
-    return psi_box_body<0>(dx - 0.5, dy - 0.5, dz - 0.5, 1.0, R2);
+    const int lane = threadIdx.x & 63;
+    double cz2[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        double cz = lz + (double)(2 * k + 1) * 0.03125;
+        cz2[k] = cz * cz;
+    }
+    double czmin = cz2[0], czmax = cz2[0];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+        czmin = cz2[k] < czmin ? cz2[k] : czmin;
+        czmax = cz2[k] > czmax ? cz2[k] : czmax;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int col = lane + 64 * r;
+        double cx = lx + (double)(2 * (col >> 4) + 1) * 0.03125;
+        double cy = ly + (double)(2 * (col & 15) + 1) * 0.03125;
+        double sxy = cx * cx + cy * cy;
+        if (sxy + czmin > R2) continue;       // no leaf of this column inside (monotone)
+        if (sxy + czmax <= R2) {              // every leaf of this column inside
+            cnt += 16;
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cnt += (sxy + cz2[k] <= R2) ? 1 : 0;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    return cnt;
+}
+
+// Cooperative Psi count: every lane of the wavefront calls this together; a
+// lane with need == true receives the count of its cell (lx, ly, lz = cell
+// corner relative to the sphere centre).
+__device__ __forceinline__ int wave_psi_resolve(bool need, double lx, double ly, double lz, double R2, int mine) {
+    unsigned long long mask = __ballot(need);
+    const int lane = threadIdx.x & 63;
+    while (mask) {
+        int l = __ffsll((long long)mask) - 1;
+        double bx = __shfl(lx, l), by = __shfl(ly, l), bz = __shfl(lz, l), br = __shfl(R2, l);
+        int c = wave_leaf_count(bx, by, bz, br);
+        if (lane == l) mine = c;
+        mask &= mask - 1;
+    }
+    return mine;
 }
 
 __device__ __forceinline__ bool centre_inside(double dx, double dy, double dz, double R) {
@@ -78,9 +113,16 @@ __device__ __forceinline__ bool far_from(double dx, double dy, double dz, double
     return fabs(dx) > R + 1.0 || fabs(dy) > R + 1.0 || fabs(dz) > R + 1.0;
 }
 
+// x - box_lo lies in (-n, 2n) because 0 <= x < n and -n <= box_lo < n.
+__device__ __forceinline__ int box_off(int x, int lo, int n) {
+    int d = x - lo;
+    d = d < 0 ? d + n : d;
+    return d >= n ? d - n : d;
+}
+
 __device__ __forceinline__ bool in_box(const PState& q, int x, int y, int z, int nx, int ny, int nz) {
-    return wrapi(x - q.box_lo[0], nx) < q.box_n[0] && wrapi(y - q.box_lo[1], ny) < q.box_n[1] &&
-           wrapi(z - q.box_lo[2], nz) < q.box_n[2];
+    return box_off(x, q.box_lo[0], nx) < q.box_n[0] && box_off(y, q.box_lo[1], ny) < q.box_n[1] &&
+           box_off(z, q.box_lo[2], nz) < q.box_n[2];
 }
 
 template <typename T>
@@ -141,6 +183,12 @@ __device__ void block_sum(double (&v)[NV]) {
     __syncthreads();
 }
 
+// Partial-sum record of (kind, particle p, chunk).
+template <typename T>
+__device__ __forceinline__ double* partial_rec(const Sim<T>& s, int kind, int p, int chunk) {
+    return s.partial + (((long)kind * s.np + p) * s.nchunk + chunk) * PSTRIDE;
+}
+
 // ---------------------------------------------------------------------------
 // Particle move (Sec. III.B) and box of this step.
 // ---------------------------------------------------------------------------
@@ -196,42 +244,54 @@ __global__ void k_move(Sim<T> s, int init) {
 // Coverage of the cells of each box: flag (centre inside, Fig. 1), owner
 // (lowest particle index), Psi = min(1, sum_p Psi_p), particle charge rho_b
 // (Psi mode: sum_p Z_p Psi_p / V_p) plus wall charge.  The previous flag and
-// owner are kept in bit1 / owner_prev for the moving-boundary update.
+// owner are kept in bit1 / owner_prev for the moving-boundary update.  The
+// loops are wavefront-uniform so that cut cells can be resolved cooperatively.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(PT) void k_geometry(Sim<T> s, int init) {
 #pragma clang fp contract(off)
     int p = blockIdx.y;
     const PState& me = s.parts[p];
-    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
-    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
-        int x, y, z;
-        box_cell(s, me, t, x, y, z);
-        if (!box_owner_is(s, p, x, y, z)) continue;
-        long c = cidx(s, x, y, z);
-        uint8_t old = s.flag[c];
+    const int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int base = blockIdx.x * PT + wave * 64; base < ncell; base += gridDim.x * PT) {
+        int t = base + lane;
+        int x = 0, y = 0, z = 0;
+        bool active = t < ncell;
+        if (active) {
+            box_cell(s, me, t, x, y, z);
+            active = box_owner_is(s, p, x, y, z);
+        }
+        long c = active ? cidx(s, x, y, z) : 0;
+        uint8_t old = active ? s.flag[c] : 0;
         uint8_t wall = old & F_WALL;
         int cur = wall ? 1 : 0;
         uint16_t ow = NO_OWNER, pso = NO_OWNER;
         double psum = 0.0;
-        double qb = s.wall_charge ? s.wall_charge[c] : 0.0;
+        double qb = (active && s.wall_charge) ? s.wall_charge[c] : 0.0;
         for (int k = 0; k < s.np; ++k) {
             const PState& q = s.parts[k];
-            if (!in_box(q, x, y, z, s.nx, s.ny, s.nz)) continue;
-            double d[3];
-            cell_disp(s, x, y, z, q, d);
-            if (far_from(d[0], d[1], d[2], q.R)) continue;
-            if (!cur && centre_inside(d[0], d[1], d[2], q.R)) {
+            bool touch = active && in_box(q, x, y, z, s.nx, s.ny, s.nz);
+            double d[3] = {0.0, 0.0, 0.0};
+            if (touch) {
+                cell_disp(s, x, y, z, q, d);
+                touch = !far_from(d[0], d[1], d[2], q.R);
+            }
+            double R2 = q.R * q.R;
+            double lx = d[0] - 0.5, ly = d[1] - 0.5, lz = d[2] - 0.5;
+            int cnt = touch ? psi_cell_class(lx, ly, lz, R2) : 0;
+            if (touch && !cur && centre_inside(d[0], d[1], d[2], q.R)) {
                 cur = 1;
                 ow = (uint16_t)k;
             }
-            int cnt = psi_count(d[0], d[1], d[2], q.R);
-            if (cnt > 0) {
+            cnt = wave_psi_resolve(touch && cnt < 0, lx, ly, lz, R2, cnt);
+            if (touch && cnt > 0) {
                 psum += (double)cnt / 4096.0;
                 pso = (pso == NO_OWNER) ? (uint16_t)k : MULTI_OWNER;
                 if (s.charge_mode == EK_CHARGE_PSI) qb += q.Z * ((double)cnt / 4096.0) / q.Vp;
             }
         }
+        if (!active) continue;
         uint8_t prev = init ? (uint8_t)cur : (uint8_t)(old & F_CUR);
         s.flag[c] = (uint8_t)(wall | (cur ? F_CUR : 0) | (prev ? F_PREV : 0));
         s.owner_prev[c] = init ? ow : s.owner[c];
@@ -264,15 +324,15 @@ __device__ __forceinline__ double rho_abs(const Sim<T>& s, const T* r, int k, lo
 template <typename T>
 __global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
 #pragma clang fp contract(off)
-    int p = blockIdx.x;
-    PState& me = s.parts[p];
+    int p = blockIdx.y;
+    const PState& me = s.parts[p];
     int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     T* f = s.f[s.cur];
     const T* rho = s.rho[s.cur];
     // 0-2 Fc, 3-5 Tc, 6..6+MAXS pool, then counts
     double acc[6 + MAXS + 5];
     for (int k = 0; k < 6 + MAXS + 5; ++k) acc[k] = 0.0;
-    for (int t = threadIdx.x; t < ncell; t += PT) {
+    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += s.nchunk * PT) {
         int x, y, z;
         box_cell(s, me, t, x, y, z);
         long c = cidx(s, x, y, z);
@@ -355,17 +415,27 @@ __global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
     }
     block_sum(acc);
     if (threadIdx.x == 0) {
-        for (int d = 0; d < 3; ++d) {
-            me.Fc[d] = acc[d];
-            me.Tc[d] = acc[3 + d];
-        }
-        for (int k = 0; k < MAXS; ++k) me.pool[k] = acc[6 + k];
-        me.ncov = (int)acc[6 + MAXS];
-        me.nvac = (int)acc[6 + MAXS + 1];
-        me.npool = (int)acc[6 + MAXS + 2];
-        me.nb = (int)acc[6 + MAXS + 3];
-        me.nflag = (int)acc[6 + MAXS + 4];
+        double* out = partial_rec(s, PART_BOUNDARY, p, blockIdx.x);
+        for (int k = 0; k < 6 + MAXS + 5; ++k) out[k] = acc[k];
     }
+}
+
+// Chunk partials of k_boundary -> particle record, summed in chunk order.
+template <typename T>
+__global__ void k_boundary_reduce(Sim<T> s) {
+    int p = blockIdx.x, k = threadIdx.x;
+    if (k >= 6 + MAXS + 5) return;
+    double v = 0.0;
+    for (int c = 0; c < s.nchunk; ++c) v += partial_rec(s, PART_BOUNDARY, p, c)[k];
+    PState& me = s.parts[p];
+    if (k < 3) me.Fc[k] = v;
+    else if (k < 6) me.Tc[k - 3] = v;
+    else if (k < 6 + MAXS) me.pool[k - 6] = v;
+    else if (k == 6 + MAXS) me.ncov = (int)v;
+    else if (k == 6 + MAXS + 1) me.nvac = (int)v;
+    else if (k == 6 + MAXS + 2) me.npool = (int)v;
+    else if (k == 6 + MAXS + 3) me.nb = (int)v;
+    else me.nflag = (int)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -497,12 +567,12 @@ __global__ __launch_bounds__(PT) void k_init_density(Sim<T> s) {
 template <typename T>
 __global__ __launch_bounds__(PT) void k_hydro_force(Sim<T> s) {
 #pragma clang fp contract(off)
-    int p = blockIdx.x;
-    PState& me = s.parts[p];
+    int p = blockIdx.y;
+    const PState& me = s.parts[p];
     int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     const T* f = s.f[s.cur];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = threadIdx.x; t < ncell; t += PT) {
+    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += s.nchunk * PT) {
         int x, y, z;
         box_cell(s, me, t, x, y, z);
         long b = cidx(s, x, y, z);
@@ -532,52 +602,49 @@ __global__ __launch_bounds__(PT) void k_hydro_force(Sim<T> s) {
         });
     }
     block_sum(acc);
-    if (threadIdx.x == 0)
-        for (int d = 0; d < 3; ++d) {
-            me.Fh[d] = acc[d];
-            me.Th[d] = acc[3 + d];
-        }
+    if (threadIdx.x == 0) {
+        double* out = partial_rec(s, PART_HYDRO, p, blockIdx.x);
+        for (int k = 0; k < 6; ++k) out[k] = acc[k];
+    }
 }
 
 template <typename T>
 __global__ __launch_bounds__(PT) void k_el_force(Sim<T> s) {
 #pragma clang fp contract(off)
-    int p = blockIdx.x;
-    PState& me = s.parts[p];
-    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    int p = blockIdx.y;
+    const PState& me = s.parts[p];
+    const int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const double R2 = me.R * me.R;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = threadIdx.x; t < ncell; t += PT) {
-        int x, y, z;
-        box_cell(s, me, t, x, y, z);
-        long c = cidx(s, x, y, z);
+    for (int base = blockIdx.x * PT; base < ncell; base += s.nchunk * PT) {
+        int t = base + threadIdx.x;
+        int x = 0, y = 0, z = 0;
+        bool active = t < ncell;
+        if (active) box_cell(s, me, t, x, y, z);
+        long c = active ? cidx(s, x, y, z) : 0;
         double qb = 0.0;
-        if (s.charge_mode == EK_CHARGE_UNIFORM) {
-            if (!(s.flag[c] & F_CUR) || s.owner[c] != p || me.nb == 0) continue;
-            qb = me.Z / (double)me.nb;
-        } else {
+        bool need = false;
+        double d[3] = {0.0, 0.0, 0.0};
+        if (active) cell_disp(s, x, y, z, me, d);
+        if (active && s.charge_mode == EK_CHARGE_UNIFORM) {
+            if ((s.flag[c] & F_CUR) && s.owner[c] == p && me.nb > 0) qb = me.Z / (double)me.nb;
+        } else if (active) {
             uint16_t po = s.psi_owner[c];
-            double psip;
-            if (po == (uint16_t)p) {
-                psip = (double)s.psi[c];
-            } else if (po == MULTI_OWNER) {
-                double d[3];
-                cell_disp(s, x, y, z, me, d);
-                if (far_from(d[0], d[1], d[2], me.R)) continue;
-                psip = (double)psi_count(d[0], d[1], d[2], me.R) / 4096.0;
-            } else {
-                continue;
-            }
-            if (psip == 0.0) continue;
-            qb = me.Z * psip / me.Vp;
+            if (po == (uint16_t)p) qb = me.Z * (double)s.psi[c] / me.Vp;
+            else if (po == MULTI_OWNER && !far_from(d[0], d[1], d[2], me.R)) need = true;
         }
+        // cells overlapped by several spheres: this sphere's own Psi
+        double lx = d[0] - 0.5, ly = d[1] - 0.5, lz = d[2] - 0.5;
+        int cnt = need ? psi_cell_class(lx, ly, lz, R2) : 0;
+        cnt = wave_psi_resolve(need && cnt < 0, lx, ly, lz, R2, cnt);
+        if (need && cnt > 0) qb = me.Z * ((double)cnt / 4096.0) / me.Vp;
+        if (qb == 0.0) continue;
         double g[3];
         g[0] = 0.5 * ((double)s.phi[cidx(s, x + 1, y, z)] - (double)s.phi[cidx(s, x - 1, y, z)]);
         g[1] = 0.5 * ((double)s.phi[cidx(s, x, y + 1, z)] - (double)s.phi[cidx(s, x, y - 1, z)]);
         g[2] = 0.5 * ((double)s.phi[cidx(s, x, y, z + 1)] - (double)s.phi[cidx(s, x, y, z - 1)]);
         double fc[3];
         for (int e = 0; e < 3; ++e) fc[e] = s.kT * qb * (s.E[e] - g[e]);
-        double d[3];
-        cell_disp(s, x, y, z, me, d);
         acc[0] += fc[0];
         acc[1] += fc[1];
         acc[2] += fc[2];
@@ -586,20 +653,36 @@ __global__ __launch_bounds__(PT) void k_el_force(Sim<T> s) {
         acc[5] += d[0] * fc[1] - d[1] * fc[0];
     }
     block_sum(acc);
-    if (threadIdx.x == 0)
-        for (int d = 0; d < 3; ++d) {
-            me.Fe[d] = acc[d];
-            me.Te[d] = acc[3 + d];
-        }
+    if (threadIdx.x == 0) {
+        double* out = partial_rec(s, PART_EL, p, blockIdx.x);
+        for (int k = 0; k < 6; ++k) out[k] = acc[k];
+    }
 }
 
-// Total force of the step and the closing half kick of velocity Verlet.
+// Total force of the step and the closing half kick of velocity Verlet.  One
+// workgroup per particle: lane k < 12 sums component k of the hydrodynamic and
+// electrostatic chunk partials in chunk order (deterministic).
 template <typename T>
 __global__ void k_finish(Sim<T> s) {
 #pragma clang fp contract(off)
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= s.np) return;
+    const int p = blockIdx.x, k = threadIdx.x;
+    __shared__ double sum[12];
+    if (k < 12) {
+        const int kind = k < 6 ? PART_HYDRO : PART_EL;
+        const int j = k < 6 ? k : k - 6;
+        double v = 0.0;
+        for (int c = 0; c < s.nchunk; ++c) v += partial_rec(s, kind, p, c)[j];
+        sum[k] = v;
+    }
+    __syncthreads();
+    if (k != 0) return;
     PState& q = s.parts[p];
+    for (int d = 0; d < 3; ++d) {
+        q.Fh[d] = sum[d];
+        q.Th[d] = sum[3 + d];
+        q.Fe[d] = sum[6 + d];
+        q.Te[d] = sum[9 + d];
+    }
     double Fn[3], Tn[3];
     for (int d = 0; d < 3; ++d) {
         Fn[d] = (q.Fh[d] + q.Fe[d]) + q.Fc[d];
@@ -708,6 +791,7 @@ __global__ __launch_bounds__(PT) void k_refill_stable(Sim<T> s) {
 // launchers
 // ---------------------------------------------------------------------------
 static int box_chunks(int box_max) { return (box_max + PT - 1) / PT < 64 ? (box_max + PT - 1) / PT : 64; }
+static_assert(6 + MAXS + 5 <= PSTRIDE, "partial record too small");
 
 template <typename T>
 void launch_move(const Sim<T>& s, hipStream_t st, int init) {
@@ -724,7 +808,8 @@ void launch_geometry(const Sim<T>& s, hipStream_t st, int init) {
 template <typename T>
 void launch_boundary(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
-    hipLaunchKernelGGL(k_boundary<T>, dim3(s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_boundary<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_boundary_reduce<T>, dim3(s.np), dim3(64), 0, st, s);
     hipLaunchKernelGGL(k_expel<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
     hipLaunchKernelGGL(k_boundary_post<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
     hipLaunchKernelGGL(k_pool<T>, dim3(256), dim3(PT), 0, st, s);
@@ -745,19 +830,19 @@ void launch_init_density(const Sim<T>& s, hipStream_t st) {
 template <typename T>
 void launch_forces(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
-    hipLaunchKernelGGL(k_el_force<T>, dim3(s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_el_force<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
 }
 
 template <typename T>
 void launch_hydro(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
-    hipLaunchKernelGGL(k_hydro_force<T>, dim3(s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_hydro_force<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
 }
 
 template <typename T>
 void launch_finish(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
-    hipLaunchKernelGGL(k_finish<T>, dim3((s.np + 63) / 64), dim3(64), 0, st, s);
+    hipLaunchKernelGGL(k_finish<T>, dim3(s.np), dim3(64), 0, st, s);
 }
 
 #define EK_INST(T)                                                     \

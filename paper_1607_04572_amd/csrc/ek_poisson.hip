@@ -20,8 +20,6 @@
 
 namespace ek {
 
-constexpr int FT = 256;  // threads per FFT workgroup
-
 template <typename T> struct V2;
 template <> struct V2<float> { using t = float2; };
 template <> struct V2<double> { using t = double2; };
@@ -58,37 +56,59 @@ __device__ __forceinline__ cpx<T> mk(T x, T y) {
     return r;
 }
 
-struct Plan {
-    int nst;
-    int r[10];
-};
-
-__device__ __forceinline__ Plan make_plan(int n) {
-    Plan p;
-    p.nst = 0;
-    while (n % 4 == 0) { p.r[p.nst++] = 4; n /= 4; }
-    while (n % 2 == 0) { p.r[p.nst++] = 2; n /= 2; }
-    while (n % 3 == 0) { p.r[p.nst++] = 3; n /= 3; }
-    return p;
+// Radix-R DFT of v[0..R) in registers (forward: e^{-2 pi i qm/R}).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_small(cpx<T> (&v)[R]) {
+    if constexpr (R == 2) {
+        cpx<T> a = cadd<T>(v[0], v[1]), b = csub<T>(v[0], v[1]);
+        v[0] = a;
+        v[1] = b;
+    } else if constexpr (R == 4) {
+        cpx<T> s02 = cadd<T>(v[0], v[2]), d02 = csub<T>(v[0], v[2]);
+        cpx<T> s13 = cadd<T>(v[1], v[3]), d13 = csub<T>(v[1], v[3]);
+        cpx<T> rot = INV ? mk<T>(-d13.y, d13.x) : mk<T>(d13.y, -d13.x);  // +i or -i times d13
+        v[0] = cadd<T>(s02, s13);
+        v[2] = csub<T>(s02, s13);
+        v[1] = cadd<T>(d02, rot);
+        v[3] = csub<T>(d02, rot);
+    } else {  // R == 3
+        const T c3 = (T)-0.5;
+        const T s3 = INV ? (T)0.86602540378443864676 : (T)-0.86602540378443864676;
+        cpx<T> s12 = cadd<T>(v[1], v[2]), d12 = csub<T>(v[1], v[2]);
+        cpx<T> m = mk<T>(v[0].x + c3 * s12.x, v[0].y + c3 * s12.y);
+        cpx<T> j = mk<T>(-s3 * d12.y, s3 * d12.x);
+        v[0] = cadd<T>(v[0], s12);
+        v[1] = cadd<T>(m, j);
+        v[2] = csub<T>(m, j);
+    }
 }
 
-// FFT of P pencils of length n stored contiguously (pencil-major) in LDS
-// buffer a, using b as scratch.  Returns the buffer holding the result.
-// Forward uses e^{-2 pi i m / n} from tw; INV uses the conjugate.
-template <typename T, bool INV>
-__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int n, int P, const cpx<T>* __restrict__ tw) {
-    Plan pl = make_plan(n);
-    int Ns = 1;
-    for (int st = 0; st < pl.nst; ++st) {
-        int R = pl.r[st];
-        int nR = n / R;
-        int span = n / (Ns * R);
-        for (int t = threadIdx.x; t < P * nR; t += blockDim.x) {
-            int pen = t / nR, j = t - pen * nR;
+// One in-place Stockham stage of radix R over P pencils of length n stored at
+// a[p * ld + index].  Every thread first loads all inputs of its butterflies
+// into registers, the workgroup synchronises, then the outputs are written to
+// the same buffer (so one LDS buffer suffices).  Butterfly b of pencil p, with
+// j = b mod (n/R) and k = j mod Ns, reads indices j + r n/R, multiplies by
+// e^{-+2 pi i k r / (Ns R)} and writes (j div Ns) Ns R + k + r Ns.
+constexpr int FT = 256;    // threads per FFT workgroup
+constexpr int FE = 16;     // pencil elements per thread (P * n <= FT * FE)
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, const cpx<T>* __restrict__ tw) {
+    constexpr int NB = (FE + R - 1) / R;
+    const int nR = n / R;
+    const int span = n / (Ns * R);
+    const int nb = P * nR;
+    cpx<T> v[NB][R];
+    int dst[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        int b = threadIdx.x + q * FT;
+        dst[q] = -1;
+        if (b < nb) {
+            int pen = b / nR, j = b - pen * nR;
             int k = j % Ns;
-            const cpx<T>* src = a + pen * n;
-            cpx<T>* dst = b + pen * n;
-            cpx<T> v[4];
+            const cpx<T>* src = a + pen * ld;
+#pragma unroll
             for (int r = 0; r < R; ++r) {
                 cpx<T> x = src[j + r * nR];
                 if (r > 0 && k > 0) {
@@ -96,41 +116,45 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int n, int P, const cpx<T>* __r
                     if (INV) w.y = -w.y;
                     x = cmul<T>(x, w);
                 }
-                v[r] = x;
+                v[q][r] = x;
             }
-            cpx<T> o[4];
-            if (R == 2) {
-                o[0] = cadd<T>(v[0], v[1]);
-                o[1] = csub<T>(v[0], v[1]);
-            } else if (R == 4) {
-                cpx<T> s02 = cadd<T>(v[0], v[2]), d02 = csub<T>(v[0], v[2]);
-                cpx<T> s13 = cadd<T>(v[1], v[3]), d13 = csub<T>(v[1], v[3]);
-                // -i * d13 (forward) or +i * d13 (inverse)
-                cpx<T> rot = INV ? mk<T>(-d13.y, d13.x) : mk<T>(d13.y, -d13.x);
-                o[0] = cadd<T>(s02, s13);
-                o[2] = csub<T>(s02, s13);
-                o[1] = cadd<T>(d02, rot);
-                o[3] = csub<T>(d02, rot);
-            } else {  // R == 3
-                const T c3 = (T)-0.5;
-                const T s3 = INV ? (T)0.86602540378443864676 : (T)-0.86602540378443864676;
-                cpx<T> s12 = cadd<T>(v[1], v[2]), d12 = csub<T>(v[1], v[2]);
-                o[0] = cadd<T>(v[0], s12);
-                cpx<T> m = mk<T>(v[0].x + c3 * s12.x, v[0].y + c3 * s12.y);
-                cpx<T> j = mk<T>(-s3 * d12.y, s3 * d12.x);  // i * s3 * d12
-                o[1] = cadd<T>(m, j);
-                o[2] = csub<T>(m, j);
-            }
-            int idxD = (j / Ns) * Ns * R + k;
-            for (int r = 0; r < R; ++r) dst[idxD + r * Ns] = o[r];
+            dst[q] = pen * ld + (j / Ns) * Ns * R + k;
         }
-        __syncthreads();
-        cpx<T>* tmp = a;
-        a = b;
-        b = tmp;
-        Ns *= R;
     }
-    return a;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if (dst[q] >= 0) {
+            dft_small<T, R, INV>(v[q]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[dst[q] + r * Ns] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// In-place FFT of P pencils (P * n <= FT * FE) in LDS; all threads participate.
+// Forward uses e^{-2 pi i m / n} from tw; INV the conjugate.
+// Radices in the order 4, 4, ..., (2), 3, 3, ...: the greedy choice below
+// takes every factor 4 first, then the remaining factor 2, then the 3s.
+template <typename T, bool INV>
+__device__ __forceinline__ void fft_lds(cpx<T>* a, int n, int P, int ld, const cpx<T>* __restrict__ tw) {
+    int Ns = 1;
+    for (int m = n; m > 1;) {
+        if (m % 4 == 0) {
+            stage<T, 4, INV>(a, n, P, ld, Ns, tw);
+            Ns *= 4;
+            m /= 4;
+        } else if (m % 2 == 0) {
+            stage<T, 2, INV>(a, n, P, ld, Ns, tw);
+            Ns *= 2;
+            m /= 2;
+        } else {
+            stage<T, 3, INV>(a, n, P, ld, Ns, tw);
+            Ns *= 3;
+            m /= 3;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -141,8 +165,7 @@ template <typename T>
 __global__ __launch_bounds__(FT) void k_fft_x_fwd(Sim<T> s, int P) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* b = a + P * s.nx;
-    const int n = s.nx;
+    const int n = s.nx, ld = n + 1;
     const int npairs = s.ny * s.nz / 2;
     const int pair0 = blockIdx.x * P;
     const T* rho = s.rho[s.cur];
@@ -161,18 +184,19 @@ __global__ __launch_bounds__(FT) void k_fft_x_fwd(Sim<T> s, int P) {
             }
             v = mk<T>(q0, q1);
         }
-        a[t] = v;
+        a[pen * ld + x] = v;
     }
     __syncthreads();
-    cpx<T>* r = fft_lds<T, false>(a, b, n, P, reinterpret_cast<const cpx<T>*>(s.tw[0]));
+    fft_lds<T, false>(a, n, P, ld, reinterpret_cast<const cpx<T>*>(s.tw[0]));
+    const cpx<T>* r = a;
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
     const int nh = s.nxh;
     for (int t = threadIdx.x; t < P * nh; t += FT) {
         int pen = t / nh, k = t - pen * nh;
         int pr = pair0 + pen;
         if (pr >= npairs) continue;
-        cpx<T> A = r[pen * n + k];
-        cpx<T> B = r[pen * n + (k == 0 ? 0 : n - k)];
+        cpx<T> A = r[pen * ld + k];
+        cpx<T> B = r[pen * ld + (k == 0 ? 0 : n - k)];
         // Q1 = (A + conj B)/2, Q2 = (A - conj B)/(2i)
         cpx<T> q1 = mk<T>((T)0.5 * (A.x + B.x), (T)0.5 * (A.y - B.y));
         cpx<T> q2 = mk<T>((T)0.5 * (A.y + B.y), (T)-0.5 * (A.x - B.x));
@@ -189,8 +213,7 @@ template <typename T>
 __global__ __launch_bounds__(FT) void k_fft_x_inv(Sim<T> s, int P) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* b = a + P * s.nx;
-    const int n = s.nx;
+    const int n = s.nx, ld = n + 1;
     const int nh = s.nxh;
     const int npairs = s.ny * s.nz / 2;
     const int pair0 = blockIdx.x * P;
@@ -209,17 +232,18 @@ __global__ __launch_bounds__(FT) void k_fft_x_inv(Sim<T> s, int P) {
                 v = mk<T>(q1.x + q2.y, -q1.y + q2.x);  // conj(q1) + i conj(q2)
             }
         }
-        a[t] = v;
+        a[pen * ld + k] = v;
     }
     __syncthreads();
-    cpx<T>* r = fft_lds<T, true>(a, b, n, P, reinterpret_cast<const cpx<T>*>(s.tw[0]));
+    fft_lds<T, true>(a, n, P, ld, reinterpret_cast<const cpx<T>*>(s.tw[0]));
     for (int t = threadIdx.x; t < P * n; t += FT) {
         int pen = t / n, x = t - pen * n;
         int pr = pair0 + pen;
         if (pr >= npairs) continue;
         long c0 = (long)(2 * pr) * n + x;
-        s.phi[c0] = r[t].x;
-        s.phi[c0 + n] = r[t].y;
+        cpx<T> v = a[pen * ld + x];
+        s.phi[c0] = v.x;
+        s.phi[c0 + n] = v.y;
     }
 }
 
@@ -229,9 +253,8 @@ __global__ __launch_bounds__(FT) void k_fft_x_inv(Sim<T> s, int P) {
 template <typename T, bool INV>
 __global__ __launch_bounds__(FT) void k_fft_y(Sim<T> s, int TX) {
     extern __shared__ unsigned char smem_raw[];
-    const int n = s.ny, nh = s.nxh;
+    const int n = s.ny, nh = s.nxh, ld = n + 1;
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* b = a + TX * n;
     int tiles = (nh + TX - 1) / TX;
     int z = blockIdx.x / tiles;
     int kx0 = (blockIdx.x - z * tiles) * TX;
@@ -239,14 +262,14 @@ __global__ __launch_bounds__(FT) void k_fft_y(Sim<T> s, int TX) {
     for (int t = threadIdx.x; t < TX * n; t += FT) {
         int y = t / TX, i = t - y * TX;
         int kx = kx0 + i;
-        a[i * n + y] = kx < nh ? S[(long)y * nh + kx] : mk<T>(0, 0);
+        a[i * ld + y] = kx < nh ? S[(long)y * nh + kx] : mk<T>(0, 0);
     }
     __syncthreads();
-    cpx<T>* r = fft_lds<T, INV>(a, b, n, TX, reinterpret_cast<const cpx<T>*>(s.tw[1]));
+    fft_lds<T, INV>(a, n, TX, ld, reinterpret_cast<const cpx<T>*>(s.tw[1]));
     for (int t = threadIdx.x; t < TX * n; t += FT) {
         int y = t / TX, i = t - y * TX;
         int kx = kx0 + i;
-        if (kx < nh) S[(long)y * nh + kx] = r[i * n + y];
+        if (kx < nh) S[(long)y * nh + kx] = a[i * ld + y];
     }
 }
 
@@ -256,9 +279,8 @@ __global__ __launch_bounds__(FT) void k_fft_y(Sim<T> s, int TX) {
 template <typename T>
 __global__ __launch_bounds__(FT) void k_fft_z_green(Sim<T> s, int TX) {
     extern __shared__ unsigned char smem_raw[];
-    const int n = s.nz, nh = s.nxh, ny = s.ny;
+    const int n = s.nz, nh = s.nxh, ny = s.ny, ld = n + 1;
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* b = a + TX * n;
     int tiles = (nh + TX - 1) / TX;
     int ky = blockIdx.x / tiles;
     int kx0 = (blockIdx.x - ky * tiles) * TX;
@@ -267,11 +289,10 @@ __global__ __launch_bounds__(FT) void k_fft_z_green(Sim<T> s, int TX) {
     for (int t = threadIdx.x; t < TX * n; t += FT) {
         int z = t / TX, i = t - z * TX;
         int kx = kx0 + i;
-        a[i * n + z] = kx < nh ? S[z * zstride + (long)ky * nh + kx] : mk<T>(0, 0);
+        a[i * ld + z] = kx < nh ? S[z * zstride + (long)ky * nh + kx] : mk<T>(0, 0);
     }
     __syncthreads();
-    cpx<T>* r = fft_lds<T, false>(a, b, n, TX, reinterpret_cast<const cpx<T>*>(s.tw[2]));
-    cpx<T>* o = (r == a) ? b : a;
+    fft_lds<T, false>(a, n, TX, ld, reinterpret_cast<const cpx<T>*>(s.tw[2]));
     const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
     for (int t = threadIdx.x; t < TX * n; t += FT) {
         int i = t / n, kz = t - i * n;
@@ -281,30 +302,31 @@ __global__ __launch_bounds__(FT) void k_fft_z_green(Sim<T> s, int TX) {
             T K2 = s.k2[0][kx] + s.k2[1][ky] + s.k2[2][kz];
             g = (kx == 0 && ky == 0 && kz == 0) ? (T)0 : scale / K2;
         }
-        cpx<T> v = r[t];
-        o[t] = mk<T>(v.x * g, v.y * g);
+        cpx<T> v = a[i * ld + kz];
+        a[i * ld + kz] = mk<T>(v.x * g, v.y * g);
     }
     __syncthreads();
-    cpx<T>* q = fft_lds<T, true>(o, r, n, TX, reinterpret_cast<const cpx<T>*>(s.tw[2]));
+    fft_lds<T, true>(a, n, TX, ld, reinterpret_cast<const cpx<T>*>(s.tw[2]));
     for (int t = threadIdx.x; t < TX * n; t += FT) {
         int z = t / TX, i = t - z * TX;
         int kx = kx0 + i;
-        if (kx < nh) S[z * zstride + (long)ky * nh + kx] = q[i * n + z];
+        if (kx < nh) S[z * zstride + (long)ky * nh + kx] = a[i * ld + z];
     }
 }
 
+// Pencils per workgroup in the x passes: P * n <= FT * FE / 2.
 template <typename T>
 static int pencils_x(int n) {
-    int P = 1024 / n;
+    int P = (FT * FE / 2) / n;
     return P < 1 ? 1 : P;
 }
 
 // Consecutive kx columns per workgroup in the y and z passes: 16 (FP32) or 8
-// (FP64) for coalesced 128-byte rows, fewer for long pencils so that the two
-// LDS buffers stay within 64 KB.
+// (FP64) for coalesced 128-byte rows, fewer for long pencils so that
+// TX * n <= FT * FE (registers of the in-place stages).
 template <typename T>
 static int tile_kx(int n) {
-    int cap = (int)(32768 / sizeof(cpx<T>)) / n;
+    int cap = (FT * FE) / n;
     int t = sizeof(T) == 4 ? 16 : 8;
     return t < cap ? t : cap;
 }
@@ -315,13 +337,13 @@ void launch_charge_poisson(const Sim<T>& s, hipStream_t st) {
     int P = pencils_x<T>(s.nx);
     int npairs = s.ny * s.nz / 2;
     int gx = (npairs + P - 1) / P;
-    size_t shx = 2 * (size_t)P * s.nx * cs;
+    size_t shx = (size_t)P * (s.nx + 1) * cs;
     hipLaunchKernelGGL(k_fft_x_fwd<T>, dim3(gx), dim3(FT), shx, st, s, P);
     int TXy = tile_kx<T>(s.ny), TXz = tile_kx<T>(s.nz);
     int tiles_y = (s.nxh + TXy - 1) / TXy, tiles_z = (s.nxh + TXz - 1) / TXz;
-    size_t shy = 2 * (size_t)TXy * s.ny * cs;
+    size_t shy = (size_t)TXy * (s.ny + 1) * cs;
     hipLaunchKernelGGL((k_fft_y<T, false>), dim3(tiles_y * s.nz), dim3(FT), shy, st, s, TXy);
-    size_t shz = 2 * (size_t)TXz * s.nz * cs;
+    size_t shz = (size_t)TXz * (s.nz + 1) * cs;
     hipLaunchKernelGGL(k_fft_z_green<T>, dim3(tiles_z * s.ny), dim3(FT), shz, st, s, TXz);
     hipLaunchKernelGGL((k_fft_y<T, true>), dim3(tiles_y * s.nz), dim3(FT), shy, st, s, TXy);
     hipLaunchKernelGGL(k_fft_x_inv<T>, dim3(gx), dim3(FT), shx, st, s, P);

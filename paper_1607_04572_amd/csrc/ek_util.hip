@@ -98,14 +98,25 @@ void launch_diagnostics(const Sim<T>& s, hipStream_t st, double* out) {
 template void launch_diagnostics<float>(const Sim<float>&, hipStream_t, double*);
 template void launch_diagnostics<double>(const Sim<double>&, hipStream_t, double*);
 
-// Plain streaming copy, 16 bytes per lane per iteration (bandwidth probe).
+// Plain streaming copy (bandwidth probe): each lane moves four independent
+// 16-byte vectors per iteration; the tail is copied one vector at a time.
 __global__ __launch_bounds__(UT) void k_copy16(float4* __restrict__ dst, const float4* __restrict__ src, long n) {
-    for (long i = (long)blockIdx.x * UT + threadIdx.x; i < n; i += (long)gridDim.x * UT) dst[i] = src[i];
+    const long stride = (long)gridDim.x * UT;
+    long i = (long)blockIdx.x * UT + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 void launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
-    long blocks = (n16 + UT - 1) / UT;
-    if (blocks > 8192) blocks = 8192;
+    long blocks = (n16 + 4 * UT - 1) / (4 * UT);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(UT), 0, st, (float4*)dst, (const float4*)src, n16);
 }
 

@@ -91,3 +91,25 @@ def test_psi_sum_capped_at_one():
     p1 = O.geometry(p, parts[:1])[2]
     p2 = O.geometry(p, parts[1:])[2]
     assert np.array_equal(psi, np.minimum(1.0, p1 + p2))
+
+
+def test_psi_recursion_equals_leaf_count_at_ties():
+    """Near ties: radii chosen so that one depth-4 leaf centre lies (in FP64)
+    exactly on the sphere.  The recursive subdivision and the plain count of
+    leaf centres with fl(fl(cx^2 + cy^2) + cz^2) <= R^2 must still agree (the
+    GPU counts leaf centres directly)."""
+    rng = np.random.default_rng(11)
+    L = O.lib()
+    t = (2 * np.arange(16) + 1) / 32.0
+    hits = 0
+    for _ in range(400):
+        d = rng.uniform(-6, 6, 3)
+        lo = d - 0.5
+        i, j, k = rng.integers(0, 16, 3)
+        cx, cy, cz = lo[0] + t[i], lo[1] + t[j], lo[2] + t[k]
+        R = float(np.sqrt((cx * cx + cy * cy) + cz * cz))
+        X, Y, Z = np.meshgrid(lo[0] + t, lo[1] + t, lo[2] + t, indexing="ij")
+        direct = int((((X * X + Y * Y) + Z * Z) <= R * R).sum())
+        assert L.or_psi_count(*d, R) == direct
+        hits += direct not in (0, 4096)
+    assert hits > 100
