@@ -40,174 +40,251 @@ __device__ __forceinline__ long cidx3(const Sim<T>& s, int x, int y, int z) {
 // ---------------------------------------------------------------------------
 // EK
 // ---------------------------------------------------------------------------
+// One LDS record per cell: NS densities, potential, Psi, velocity, boundary
+// flag, padded to a multiple of 4 elements (vector LDS reads).
 template <typename T, int NS>
-struct CellEK {
-    T r[NS];
-    T psi, phi, ux, uy, uz;
-    bool wall;
+struct alignas(16) RecEK {
+    static constexpr int NV = ((NS + 6) + 3) / 4 * 4;
+    T v[NV];
+    __device__ __forceinline__ T r(int k) const { return v[k]; }
+    __device__ __forceinline__ T phi() const { return v[NS]; }
+    __device__ __forceinline__ T psi() const { return v[NS + 1]; }
+    __device__ __forceinline__ T ux() const { return v[NS + 2]; }
+    __device__ __forceinline__ T uy() const { return v[NS + 3]; }
+    __device__ __forceinline__ T uz() const { return v[NS + 4]; }
+    __device__ __forceinline__ bool wall() const { return v[NS + 5] != (T)0; }
 };
 
-template <typename T, int H>
-__device__ __forceinline__ T adv_frac(T ux, T uy, T uz, int sgn) {
-    constexpr int sx = hx(H), sy = hy(H), sz = hz(H);
-    T g = (T)1;
-    T u[3] = {ux, uy, uz};
-    int sv[3] = {sx * sgn, sy * sgn, sz * sgn};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        T a = fabs(u[d]);
-        if (sv[d] == 0) g *= ((T)1 - a);
-        else g *= ((sv[d] > 0 && u[d] > (T)0) || (sv[d] < 0 && u[d] < (T)0)) ? a : (T)0;
-    }
-    return g;
+// Per-species constants of the link flux, hoisted out of the cell loop.
+template <typename T, int NS>
+struct EKConst {
+    T D[NS], hz[NS], ref[NS], ref2hz[NS];
+    T Es[13], coef[13];
+};
+
+// Fraction of a cell moving with velocity u that lands in the neighbour at
+// offset s along one axis: |u| if s has the sign of u, 1 - |u| if s = 0, else 0.
+template <typename T, int SX>
+__device__ __forceinline__ T vof_axis(T u) {
+    if constexpr (SX > 0) return u > (T)0 ? u : (T)0;
+    else if constexpr (SX < 0) return u < (T)0 ? -u : (T)0;
+    else return (T)1 - fabs(u);
 }
 
-template <typename T, bool DEV, int NS, int H>
-__device__ __forceinline__ void link_flux(const Sim<T>& s, const CellEK<T, NS>& a, const CellEK<T, NS>& b,
-                                          const T (&Es)[13], const T (&coef)[13], T (&jt)[NS], T (&gd)[NS]) {
-    if (a.wall || b.wall) {
+// g(s; u) = product over the axes, in axis order.
+template <typename T, int SX, int SY, int SZ>
+__device__ __forceinline__ T vof_frac(T ux, T uy, T uz) {
+    return (vof_axis<T, SX>(ux) * vof_axis<T, SY>(uy)) * vof_axis<T, SZ>(uz);
+}
+
+// Flux on the link a -> b along half-direction H: total flux jt[k] and the
+// diffusive/migrative part divided by D, summed over species, in gsum.
+// CLEAN: neither end is a boundary cell and both have Psi = 0; the general
+// formula then reduces exactly (multiplications by 1 and additions of 0 are
+// exact) to the clean one, so both evaluations of a link give the same bits
+// whichever path they take.
+template <typename T, bool DEV, int NS, int H, bool CLEAN>
+__device__ __forceinline__ void link_flux(const Sim<T>& s, const RecEK<T, NS>& a, const RecEK<T, NS>& b,
+                                          const EKConst<T, NS>& K, T (&jt)[NS], T& gsum) {
+    constexpr int SX = hx(H), SY = hy(H), SZ = hz(H);
+    gsum = (T)0;
+    if constexpr (!CLEAN) {
+        if (a.wall() || b.wall()) {
 #pragma unroll
-        for (int k = 0; k < NS; ++k) jt[k] = gd[k] = (T)0;
-        return;
+            for (int k = 0; k < NS; ++k) jt[k] = (T)0;
+            return;
+        }
     }
-    T pa = s.pv ? a.psi : (T)0;
-    T pb = s.pv ? b.psi : (T)0;
-    T oa = (T)1 - pa, ob = (T)1 - pb;
-    T dphi = (a.phi - b.phi) + Es[H];
-    T ga = adv_frac<T, H>(a.ux, a.uy, a.uz, +1);
-    T gb = adv_frac<T, H>(b.ux, b.uy, b.uz, -1);
+    const T dphi = (a.phi() - b.phi()) + K.Es[H];
+    const T ga = vof_frac<T, SX, SY, SZ>(a.ux(), a.uy(), a.uz());
+    const T gb = vof_frac<T, -SX, -SY, -SZ>(b.ux(), b.uy(), b.uz());
+    T pa = (T)0, pb = (T)0, oa = (T)1, ob = (T)1;
+    if constexpr (!CLEAN) {
+        pa = s.pv ? a.psi() : (T)0;
+        pb = s.pv ? b.psi() : (T)0;
+        oa = (T)1 - pa;
+        ob = (T)1 - pb;
+    }
+    const T dg = ga - gb;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        T ra = a.r[k], rb = b.r[k];
-        T g = (T)0;
-        T A = ra * ob - rb * oa;
-        T B = ra * ob + rb * oa;
-        T adv = ra * ga - rb * gb;
-        if constexpr (DEV) {
-            T ref = (T)s.rho_ref[k];
-            A += ref * (pa - pb);
-            B += ref * (oa + ob);
-            adv += ref * (ga - gb);
+        const T ra = a.r(k), rb = b.r(k);
+        T A, B;
+        if constexpr (CLEAN) {
+            A = ra - rb;
+            B = ra + rb;
+        } else {
+            A = ra * ob - rb * oa;
+            B = ra * ob + rb * oa;
+            if constexpr (DEV) A += K.ref[k] * (pa - pb);
         }
-        if constexpr (H < 9) g = (A + (T)0.5 * (T)s.z[k] * B * dphi) * coef[H];
-        gd[k] = g;
-        jt[k] = (T)s.D[k] * g + adv;
+        T adv = ra * ga - rb * gb;
+        T mig = K.hz[k] * B;
+        if constexpr (DEV) {
+            // reference density terms: B += 2 ref (clean) or ref (oa + ob)
+            if constexpr (CLEAN) mig += K.ref2hz[k];
+            else mig += K.hz[k] * (K.ref[k] * (oa + ob));
+            adv += K.ref[k] * dg;
+        }
+        T g = (T)0;
+        if constexpr (H < 9) {
+            g = (A + mig * dphi) * K.coef[H];
+            gsum += g;
+        }
+        jt[k] = K.D[k] * g + adv;
     }
 }
 
-// LDS window: a (TXW+2) x (TYW+2) window of every input field for three
-// consecutive z-planes (z-1, z, z+1), marched along z.
+// LDS window: (TXW+2) x (TYW+2) records for three consecutive z-planes
+// (z-1, z, z+1), marched along z.
 template <typename T, int NS, int TXW, int TYW>
 struct EKShared {
     static constexpr int WX = TXW + 2, WY = TYW + 2, WPL = WX * WY;
-    T r[NS][3][WPL];
-    float psi[3][WPL];
-    T phi[3][WPL];
-    T u[3][3][WPL];
-    uint8_t fl[3][WPL];
+    RecEK<T, NS> rec[3][WPL];
+    int dirty[3];
 };
 
+// Load one plane; returns whether it holds a boundary cell or a partial volume.
 template <typename T, int NS, int TXW, int TYW>
-__device__ __forceinline__ void ek_load_plane(const Sim<T>& s, EKShared<T, NS, TXW, TYW>& sh, int slot, int x0,
+__device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, TXW, TYW>& sh, int slot, int x0,
                                               int y0, int z, const T* __restrict__ rin) {
     using SH = EKShared<T, NS, TXW, TYW>;
     int zz = wrapi(z, s.nz);
+    bool dirty = false;
     for (int t = threadIdx.x; t < SH::WPL; t += TXW * TYW) {
         int i = t % SH::WX, j = t / SH::WX;
         int x = wrapi(x0 + i - 1, s.nx), y = wrapi(y0 + j - 1, s.ny);
         long c = cidx3(s, x, y, zz);
+        RecEK<T, NS> r;
 #pragma unroll
-        for (int k = 0; k < NS; ++k) sh.r[k][slot][t] = rin[(long)k * s.N + c];
-        sh.psi[slot][t] = s.psi[c];
-        sh.phi[slot][t] = s.phi[c];
-        sh.u[0][slot][t] = s.u[c];
-        sh.u[1][slot][t] = s.u[s.N + c];
-        sh.u[2][slot][t] = s.u[2 * s.N + c];
-        sh.fl[slot][t] = s.flag[c];
+        for (int k = 0; k < NS; ++k) r.v[k] = rin[(long)k * s.N + c];
+        float psi = s.psi[c];
+        uint8_t fl = s.flag[c];
+        r.v[NS] = s.phi[c];
+        r.v[NS + 1] = (T)psi;
+        r.v[NS + 2] = s.u[c];
+        r.v[NS + 3] = s.u[s.N + c];
+        r.v[NS + 4] = s.u[2 * s.N + c];
+        r.v[NS + 5] = (fl & F_CUR) ? (T)1 : (T)0;
+#pragma unroll
+        for (int k = NS + 6; k < RecEK<T, NS>::NV; ++k) r.v[k] = (T)0;
+        sh.rec[slot][t] = r;
+        dirty |= (psi != 0.0f) || (fl & F_CUR);
     }
+    return dirty;
 }
 
-template <typename T, int NS, int TXW, int TYW>
-__device__ __forceinline__ CellEK<T, NS> ek_cell(const EKShared<T, NS, TXW, TYW>& sh, int slot, int t) {
-    CellEK<T, NS> c;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) c.r[k] = sh.r[k][slot][t];
-    c.psi = (T)sh.psi[slot][t];
-    c.phi = sh.phi[slot][t];
-    c.ux = sh.u[0][slot][t];
-    c.uy = sh.u[1][slot][t];
-    c.uz = sh.u[2][slot][t];
-    c.wall = (sh.fl[slot][t] & F_CUR) != 0;
-    return c;
+// Block -> tile map that keeps neighbouring tiles on one XCD: workgroups are
+// dispatched round-robin over the 8 XCDs (each with its own L2), so tile
+// (bid mod 8) * (n / 8) + bid / 8 puts consecutive tiles, whose halo cache
+// lines overlap, on the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+    constexpr int NXCD = 8;
+    if (n % NXCD) return bid;
+    return (bid % NXCD) * (n / NXCD) + bid / NXCD;
 }
 
-// Grid: ceil(nx/TXW) x ceil(ny/TYW) x z-chunks; each workgroup marches ZC planes.
-template <typename T, bool DEV, int NS, int TXW, int TYW>
-__global__ __launch_bounds__(TXW* TYW) void k_ek(Sim<T> s, int ZC) {
+template <typename T, bool DEV, int NS, int TXW, int TYW, bool CLEAN>
+__device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T, NS, TXW, TYW>& sh, int s0, int sm,
+                                               int sp, int ctr, const EKConst<T, NS>& K, T (&dr)[NS], T (&fe)[3]) {
     using SH = EKShared<T, NS, TXW, TYW>;
-    __shared__ SH sh;
-    const int x0 = blockIdx.x * TXW, y0 = blockIdx.y * TYW, zbeg = blockIdx.z * ZC;
-    const T* __restrict__ rin = s.rho[s.cur];
-    T* __restrict__ rout = s.rho[s.cur ^ 1];
-    T Es[13], coef[13];
+    const RecEK<T, NS> me = sh.rec[s0][ctr];
     sfor<13>([&](auto HH) {
         constexpr int h = HH;
-        Es[h] = (T)(s.E[0] * hx(h) + s.E[1] * hy(h) + s.E[2] * hz(h));
-        coef[h] = (T)(1.0 / ((1.0 + 2.0 * 1.4142135623730950488) * hlen(h)));
+        constexpr int ox = hx(h), oy = hy(h), oz = hz(h);
+        const int up = ctr + oy * SH::WX + ox, dn = ctr - oy * SH::WX - ox;
+        const int sup = oz == 0 ? s0 : (oz > 0 ? sp : sm);
+        const int sdn = oz == 0 ? s0 : (oz > 0 ? sm : sp);
+        const RecEK<T, NS> cu = sh.rec[sup][up];
+        const RecEK<T, NS> cd = sh.rec[sdn][dn];
+        T jt1[NS], jt2[NS], g1, g2;
+        link_flux<T, DEV, NS, h, CLEAN>(s, me, cu, K, jt1, g1);
+        link_flux<T, DEV, NS, h, CLEAN>(s, cd, me, K, jt2, g2);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) dr[k] += jt2[k] - jt1[k];
+        if constexpr (h < 9) {
+            // each link's friction is shared by its two cells (scaled by kT/2 below)
+            const T g = g1 + g2;
+            if constexpr (ox > 0) fe[0] += g;
+            if constexpr (ox < 0) fe[0] -= g;
+            if constexpr (oy > 0) fe[1] += g;
+            if constexpr (oy < 0) fe[1] -= g;
+            if constexpr (oz > 0) fe[2] += g;
+            if constexpr (oz < 0) fe[2] -= g;
+        }
     });
+}
+
+// Grid: tiles of TXW x TYW cells in x-y times z-chunks of ZC planes, flattened
+// and mapped with xcd_tile; each workgroup marches its ZC planes.
+template <typename T, bool DEV, int NS, int TXW, int TYW>
+__global__ __launch_bounds__(TXW* TYW) void k_ek(Sim<T> s, int ZC, int gx, int gy, int ntiles) {
+    using SH = EKShared<T, NS, TXW, TYW>;
+    __shared__ SH sh;
+    const int tile = xcd_tile(blockIdx.x, ntiles);
+    const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+    const int x0 = bx * TXW, y0 = by * TYW, zbeg = bz * ZC;
+    const T* __restrict__ rin = s.rho[s.cur];
+    T* __restrict__ rout = s.rho[s.cur ^ 1];
+    EKConst<T, NS> K;
+    sfor<13>([&](auto HH) {
+        constexpr int h = HH;
+        K.Es[h] = (T)(s.E[0] * hx(h) + s.E[1] * hy(h) + s.E[2] * hz(h));
+        K.coef[h] = (T)(1.0 / ((1.0 + 2.0 * 1.4142135623730950488) * hlen(h)));
+    });
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        K.D[k] = (T)s.D[k];
+        K.hz[k] = (T)(0.5 * s.z[k]);
+        K.ref[k] = (T)s.rho_ref[k];
+        K.ref2hz[k] = (T)(0.5 * s.z[k]) * ((T)s.rho_ref[k] * (T)2);
+    }
     const T half_kT = (T)(0.5 * s.kT);
-    ek_load_plane<T, NS, TXW, TYW>(s, sh, (zbeg + 2) % 3, x0, y0, zbeg - 1, rin);
-    ek_load_plane<T, NS, TXW, TYW>(s, sh, zbeg % 3, x0, y0, zbeg, rin);
+    {
+        bool d0 = ek_load_plane<T, NS, TXW, TYW>(s, sh, (zbeg + 2) % 3, x0, y0, zbeg - 1, rin);
+        bool d1 = ek_load_plane<T, NS, TXW, TYW>(s, sh, zbeg % 3, x0, y0, zbeg, rin);
+        int a0 = __syncthreads_or(d0), a1 = __syncthreads_or(d1);
+        if (threadIdx.x == 0) {
+            sh.dirty[(zbeg + 2) % 3] = a0;
+            sh.dirty[zbeg % 3] = a1;
+        }
+    }
     const int tx = threadIdx.x % TXW, ty = threadIdx.x / TXW;
     const int x = x0 + tx, y = y0 + ty;
     const bool valid = x < s.nx && y < s.ny;
     const int zend = zbeg + ZC < s.nz ? zbeg + ZC : s.nz;
     for (int z = zbeg; z < zend; ++z) {
-        ek_load_plane<T, NS, TXW, TYW>(s, sh, (z + 1) % 3, x0, y0, z + 1, rin);
+        bool dn = ek_load_plane<T, NS, TXW, TYW>(s, sh, (z + 1) % 3, x0, y0, z + 1, rin);
+        int an = __syncthreads_or(dn);
+        if (threadIdx.x == 0) sh.dirty[(z + 1) % 3] = an;
         __syncthreads();
+        const int sm = (z + 2) % 3, s0 = z % 3, sp = (z + 1) % 3;
+        const bool clean = !(sh.dirty[0] | sh.dirty[1] | sh.dirty[2]);
         if (valid) {
-            const int sm = (z + 2) % 3, s0 = z % 3, sp = (z + 1) % 3;
             const int ctr = (ty + 1) * SH::WX + (tx + 1);
             long c = cidx3(s, x, y, z);
-            CellEK<T, NS> me = ek_cell<T, NS, TXW, TYW>(sh, s0, ctr);
+            const bool wall = sh.rec[s0][ctr].wall();
             T dr[NS];
             T fe[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
             for (int k = 0; k < NS; ++k) dr[k] = (T)0;
-            if (!me.wall) {
-                sfor<13>([&](auto HH) {
-                    constexpr int h = HH;
-                    constexpr int ox = hx(h), oy = hy(h), oz = hz(h);
-                    const int up = ctr + oy * SH::WX + ox, dn = ctr - oy * SH::WX - ox;
-                    const int sup = oz == 0 ? s0 : (oz > 0 ? sp : sm);
-                    const int sdn = oz == 0 ? s0 : (oz > 0 ? sm : sp);
-                    CellEK<T, NS> cu = ek_cell<T, NS, TXW, TYW>(sh, sup, up);
-                    CellEK<T, NS> cd = ek_cell<T, NS, TXW, TYW>(sh, sdn, dn);
-                    T jt1[NS], gd1[NS], jt2[NS], gd2[NS];
-                    link_flux<T, DEV, NS, h>(s, me, cu, Es, coef, jt1, gd1);
-                    link_flux<T, DEV, NS, h>(s, cd, me, Es, coef, jt2, gd2);
-#pragma unroll
-                    for (int k = 0; k < NS; ++k) {
-                        dr[k] += -jt1[k] + jt2[k];
-                        if constexpr (h < 9) {
-                            T g = half_kT * (gd1[k] + gd2[k]);
-                            if constexpr (ox != 0) fe[0] += g * (T)ox;
-                            if constexpr (oy != 0) fe[1] += g * (T)oy;
-                            if constexpr (oz != 0) fe[2] += g * (T)oz;
-                        }
-                    }
-                });
-            }
+            if (clean)
+                ek_cell_update<T, DEV, NS, TXW, TYW, true>(s, sh, s0, sm, sp, ctr, K, dr, fe);
+            else if (!wall)
+                ek_cell_update<T, DEV, NS, TXW, TYW, false>(s, sh, s0, sm, sp, ctr, K, dr, fe);
+            fe[0] *= half_kT;
+            fe[1] *= half_kT;
+            fe[2] *= half_kT;
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
                 T out;
-                if (me.wall) out = DEV ? (T)(-s.rho_ref[k]) : (T)0;
-                else out = me.r[k] + dr[k];
-                rout[(long)k * s.N + c] = out;
+                if (wall) out = DEV ? (T)(-s.rho_ref[k]) : (T)0;
+                else out = sh.rec[s0][ctr].r(k) + dr[k];
+                __builtin_nontemporal_store(out, &rout[(long)k * s.N + c]);
             }
-            s.fext[c] = fe[0];
-            s.fext[s.N + c] = fe[1];
-            s.fext[2 * s.N + c] = fe[2];
+            __builtin_nontemporal_store(fe[0], &s.fext[c]);
+            __builtin_nontemporal_store(fe[1], &s.fext[s.N + c]);
+            __builtin_nontemporal_store(fe[2], &s.fext[2 * s.N + c]);
         }
         __syncthreads();
     }
@@ -312,11 +389,12 @@ __global__ __launch_bounds__(BT) void k_lb(Sim<T> s) {
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV, int NS>
 static void launch_ek_ns(const Sim<T>& s, hipStream_t st) {
-    constexpr int TXW = sizeof(T) == 4 ? 32 : 16, TYW = 8;
+    constexpr int TXW = sizeof(T) == 4 ? 64 : 32, TYW = 4;
     int gx = (s.nx + TXW - 1) / TXW, gy = (s.ny + TYW - 1) / TYW;
-    int ZC = 8;
+    int ZC = 16;
     int gz = (s.nz + ZC - 1) / ZC;
-    hipLaunchKernelGGL((k_ek<T, DEV, NS, TXW, TYW>), dim3(gx, gy, gz), dim3(TXW * TYW), 0, st, s, ZC);
+    int nt = gx * gy * gz;
+    hipLaunchKernelGGL((k_ek<T, DEV, NS, TXW, TYW>), dim3(nt), dim3(TXW * TYW), 0, st, s, ZC, gx, gy, nt);
 }
 
 template <typename T>
