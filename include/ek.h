@@ -219,6 +219,58 @@ int ek_synchronize(ek_ctx* c);
 int ek_destroy(ek_ctx* c);
 const char* ek_strerror(int code);
 
+/* ---------------------------------------------------------------------------
+ * Serving form: many independent FP32 simulations of different box sizes and
+ * particle counts resident in one device arena and advanced together.  Each
+ * kernel of a step runs once for the whole batch (persistent workgroups walk
+ * the concatenated work of all slots), and the step is a HIP graph captured
+ * once, so requests can be admitted and retired between steps without
+ * re-capturing.  Every simulation's arithmetic is independent of the others:
+ * a request gives the same bits alone and in any mix.
+ * ------------------------------------------------------------------------- */
+typedef struct ek_batch ek_batch;
+
+typedef struct {
+    double x[3], v[3];            /* centre and initial velocity */
+    double radius, charge, mass;  /* as for ek_add_sphere */
+    int mode;                     /* EK_FREE | EK_PRESCRIBED | EK_FIXED */
+} ek_sphere;
+
+#define EK_BATCH_MAX_SLOTS 64
+
+/* Create a batch over `arena_bytes` of device memory (the caller's `arena`,
+ * or allocated when NULL) for simulations with `n_species` species, ordered
+ * on `stream` (NULL: the library creates one).  Errors: INVALID_ARG, OOM. */
+int ek_batch_create(size_t arena_bytes, int n_species, void* stream, void* arena, ek_batch** out);
+
+/* Admit one request: parameters (precision must be EK_FP32_DEV, n_species as
+ * the batch; stream/arena/max_particles are set by the batch), its spheres,
+ * an optional initial density (n_species * N doubles, or NULL for the means)
+ * and the number of steps to run.  Returns the slot.  EK_ERR_NO_SPACE when no
+ * slot or no contiguous arena range of the request's footprint is free.
+ * Synchronises the batch stream. */
+int ek_batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
+                   const double* initial_density, long long n_steps, int* slot);
+
+/* Enqueue k batched steps; slots that reach their requested steps stop. */
+int ek_batch_step(ek_batch* b, int k);
+
+/* Slots whose requested steps are all done and not yet collected (at most
+ * cap of them written to done_slots).  Synchronises. */
+int ek_batch_poll(ek_batch* b, int* done_slots, int cap, int* n_done);
+
+/* Copy a slot's particles (first n) and diagnostics (either may be NULL) and
+ * free the slot and its memory.  Synchronises. */
+int ek_batch_collect(ek_batch* b, int slot, ek_particle* out, int n, ek_diag* diag);
+
+/* A field of a live slot, as ek_get_fields (tests).  Synchronises. */
+int ek_batch_get_fields(ek_batch* b, int slot, int field, void* host, size_t bytes);
+
+/* Number of slots still stepping and their total cells. */
+int ek_batch_active(ek_batch* b, int* n_active, long long* cells);
+
+int ek_batch_destroy(ek_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

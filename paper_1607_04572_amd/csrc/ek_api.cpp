@@ -880,3 +880,319 @@ int ek_destroy(ek_ctx* c) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Serving form
+// ===========================================================================
+#include <map>
+
+struct ek_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    unsigned char* arena = nullptr;
+    size_t bytes = 0;
+    bool own_arena = false;
+    BatchTable* dtab = nullptr;
+    std::map<size_t, size_t> free_ranges;  // offset -> size
+    struct Slot {
+        bool used = false, on_device = false, reported = false;
+        ek_ctx* ctx = nullptr;
+        size_t off = 0, size = 0;
+        long long cells = 0;
+    } slot[MAX_SLOTS];
+    BatchTable h{};
+    int ns = 0;
+    bool dirty = true;
+    hipGraphExec_t graph = nullptr;
+    int err = EK_OK;
+};
+
+namespace {
+
+constexpr size_t SLOT_ALIGN = 4096;
+
+bool range_alloc(ek_batch* b, size_t need, size_t* off) {
+    need = (need + SLOT_ALIGN - 1) & ~(SLOT_ALIGN - 1);
+    for (auto it = b->free_ranges.begin(); it != b->free_ranges.end(); ++it) {
+        if (it->second >= need) {
+            *off = it->first;
+            size_t rest = it->second - need;
+            size_t roff = it->first + need;
+            b->free_ranges.erase(it);
+            if (rest) b->free_ranges[roff] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void range_free(ek_batch* b, size_t off, size_t size) {
+    size = (size + SLOT_ALIGN - 1) & ~(SLOT_ALIGN - 1);
+    auto it = b->free_ranges.emplace(off, size).first;
+    auto nx = std::next(it);
+    if (nx != b->free_ranges.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        b->free_ranges.erase(nx);
+    }
+    if (it != b->free_ranges.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            b->free_ranges.erase(it);
+        }
+    }
+}
+
+#define BCHK(b, x)                    \
+    do {                              \
+        if ((x) != hipSuccess) {      \
+            (b)->err = EK_ERR_DEVICE; \
+            return EK_ERR_DEVICE;     \
+        }                             \
+    } while (0)
+
+// Bring the device-owned parts (ping-pong index, steps, activity) of the
+// slots already on the device into the host mirror.
+int pull_state(ek_batch* b) {
+    BCHK(b, hipStreamSynchronize(b->stream));
+    BatchTable* t = new (std::nothrow) BatchTable;
+    if (!t) return EK_ERR_OOM;
+    hipError_t e = hipMemcpy(t, b->dtab, sizeof(BatchTable), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        delete t;
+        b->err = EK_ERR_DEVICE;
+        return EK_ERR_DEVICE;
+    }
+    for (int i = 0; i < MAX_SLOTS; ++i) {
+        if (!b->slot[i].used || !b->slot[i].on_device) continue;
+        b->h.sims[i].cur = t->sims[i].cur;
+        b->h.step[i] = t->step[i];
+        b->h.active[i] = t->active[i];
+        b->slot[i].ctx->set_cur(t->sims[i].cur);
+        b->slot[i].ctx->step = t->step[i];
+    }
+    delete t;
+    return EK_OK;
+}
+
+int push_table(ek_batch* b) {
+    int r = pull_state(b);
+    if (r) return r;
+    int n = 0;
+    for (int i = 0; i < MAX_SLOTS; ++i)
+        if (b->slot[i].used) n = i + 1;
+    b->h.nsims = n;
+    for (int k = 0; k < KK_N; ++k) b->h.start[k][0] = 0;
+    for (int i = 0; i < n; ++i) {
+        bool live = b->slot[i].used && b->h.active[i];
+        Grids<float> g = grids_of<float>(b->h.sims[i]);
+        for (int k = 0; k < KK_N; ++k) b->h.start[k][i + 1] = b->h.start[k][i] + (live ? g.n[k] : 0);
+    }
+    BCHK(b, hipMemcpyAsync(b->dtab, &b->h, sizeof(BatchTable), hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    for (int i = 0; i < n; ++i)
+        if (b->slot[i].used) b->slot[i].on_device = true;
+    b->dirty = false;
+    return EK_OK;
+}
+
+void enqueue_batch_step(ek_batch* b) {
+    launch_batch_particles_pre(b->dtab, b->stream);
+    launch_batch_poisson(b->dtab, b->stream);
+    launch_batch_ek(b->dtab, b->ns, b->stream);
+    launch_batch_hydro(b->dtab, b->stream);
+    launch_batch_lb(b->dtab, b->stream);
+    launch_batch_particles_post(b->dtab, b->stream);
+    launch_batch_flip(b->dtab, b->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ek_batch_create(size_t arena_bytes, int n_species, void* stream, void* arena, ek_batch** out) {
+    if (!out || n_species < 1 || n_species > EK_MAX_SPECIES || arena_bytes < (size_t)(64 << 20))
+        return EK_ERR_INVALID_ARG;
+    *out = nullptr;
+    ek_batch* b = new (std::nothrow) ek_batch();
+    if (!b) return EK_ERR_OOM;
+    b->ns = n_species;
+    b->bytes = arena_bytes;
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return EK_ERR_DEVICE;
+        }
+        b->own_stream = true;
+    }
+    if (arena) {
+        b->arena = (unsigned char*)arena;
+    } else {
+        if (hipMalloc(&b->arena, arena_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            b->arena = nullptr;
+            ek_batch_destroy(b);
+            return EK_ERR_OOM;
+        }
+        b->own_arena = true;
+    }
+    b->dtab = (BatchTable*)b->arena;
+    size_t data0 = (sizeof(BatchTable) + SLOT_ALIGN - 1) & ~(SLOT_ALIGN - 1);
+    b->free_ranges[data0] = (arena_bytes - data0) & ~(SLOT_ALIGN - 1);
+    std::memset(&b->h, 0, sizeof(BatchTable));
+    if (hipMemcpy(b->dtab, &b->h, sizeof(BatchTable), hipMemcpyHostToDevice) != hipSuccess) {
+        ek_batch_destroy(b);
+        return EK_ERR_DEVICE;
+    }
+    *out = b;
+    return EK_OK;
+}
+
+int ek_batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
+                   const double* initial_density, long long n_steps, int* slot) {
+    if (!b || !p || (n_spheres > 0 && !spheres) || n_spheres < 0 || n_steps < 0) return EK_ERR_INVALID_ARG;
+    if (b->err) return b->err;
+    if (p->precision != EK_FP32_DEV || p->n_species != b->ns) return EK_ERR_INVALID_ARG;
+    int i = 0;
+    while (i < MAX_SLOTS && b->slot[i].used) ++i;
+    if (i == MAX_SLOTS) return EK_ERR_NO_SPACE;
+    ek_params q = *p;
+    q.max_particles = n_spheres > 0 ? n_spheres : 1;
+    q.stream = b->stream;
+    q.arena = nullptr;
+    q.arena_bytes = 0;
+    size_t need = 0;
+    int r = ek_query_footprint(&q, &need);
+    if (r) return r;
+    size_t off = 0;
+    if (!range_alloc(b, need, &off)) return EK_ERR_NO_SPACE;
+    q.arena = b->arena + off;
+    q.arena_bytes = need;
+    ek_ctx* c = nullptr;
+    r = ek_create(&q, &c);
+    if (r) {
+        range_free(b, off, need);
+        return r;
+    }
+    for (int k = 0; k < n_spheres && !r; ++k)
+        r = ek_add_sphere(c, spheres[k].x, spheres[k].radius, spheres[k].charge, spheres[k].mass, spheres[k].v,
+                          spheres[k].mode, nullptr);
+    if (!r && initial_density)
+        r = ek_set_fields(c, EK_FIELD_DENSITY, initial_density, (size_t)q.n_species * c->N * sizeof(double));
+    if (!r) r = ek_prepare(c);
+    if (r) {
+        ek_destroy(c);
+        range_free(b, off, need);
+        return r;
+    }
+    ek_batch::Slot& s = b->slot[i];
+    s.used = true;
+    s.on_device = false;
+    s.reported = false;
+    s.ctx = c;
+    s.off = off;
+    s.size = need;
+    s.cells = c->N;
+    b->h.sims[i] = c->sf;
+    b->h.step[i] = 0;
+    b->h.target[i] = n_steps;
+    b->h.active[i] = n_steps > 0 ? 1 : 0;
+    b->dirty = true;
+    if (slot) *slot = i;
+    return EK_OK;
+}
+
+int ek_batch_step(ek_batch* b, int k) {
+    if (!b || k < 0) return EK_ERR_INVALID_ARG;
+    if (b->err) return b->err;
+    if (b->dirty) {
+        int r = push_table(b);
+        if (r) return r;
+    }
+    if (!b->graph) {
+        hipGraph_t g = nullptr;
+        BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_batch_step(b);
+        BCHK(b, hipStreamEndCapture(b->stream, &g));
+        hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        BCHK(b, e);
+    }
+    for (int i = 0; i < k; ++i) BCHK(b, hipGraphLaunch(b->graph, b->stream));
+    return EK_OK;
+}
+
+int ek_batch_poll(ek_batch* b, int* done_slots, int cap, int* n_done) {
+    if (!b || !n_done || (cap > 0 && !done_slots)) return EK_ERR_INVALID_ARG;
+    if (b->err) return b->err;
+    int r = pull_state(b);
+    if (r) return r;
+    int n = 0;
+    for (int i = 0; i < MAX_SLOTS; ++i) {
+        ek_batch::Slot& s = b->slot[i];
+        if (!s.used || s.reported || !s.on_device) continue;
+        if (b->h.step[i] >= b->h.target[i]) {
+            if (n < cap) {
+                done_slots[n++] = i;
+                s.reported = true;
+            }
+        }
+    }
+    *n_done = n;
+    return EK_OK;
+}
+
+int ek_batch_get_fields(ek_batch* b, int slot, int field, void* host, size_t bytes) {
+    if (!b || slot < 0 || slot >= MAX_SLOTS || !b->slot[slot].used) return EK_ERR_INVALID_ARG;
+    if (b->err) return b->err;
+    int r = pull_state(b);
+    if (r) return r;
+    return ek_get_fields(b->slot[slot].ctx, field, host, bytes);
+}
+
+int ek_batch_collect(ek_batch* b, int slot, ek_particle* out, int n, ek_diag* diag) {
+    if (!b || slot < 0 || slot >= MAX_SLOTS || !b->slot[slot].used) return EK_ERR_INVALID_ARG;
+    if (b->err) return b->err;
+    int r = pull_state(b);
+    if (r) return r;
+    ek_batch::Slot& s = b->slot[slot];
+    if (out && n > 0) r = ek_get_particles(s.ctx, out, n);
+    if (!r && diag) r = ek_get_diagnostics(s.ctx, diag);
+    if (r) return r;
+    ek_destroy(s.ctx);
+    range_free(b, s.off, s.size);
+    s = ek_batch::Slot();
+    b->h.active[slot] = 0;
+    b->dirty = true;
+    return EK_OK;
+}
+
+int ek_batch_active(ek_batch* b, int* n_active, long long* cells) {
+    if (!b) return EK_ERR_INVALID_ARG;
+    int n = 0;
+    long long c = 0;
+    for (int i = 0; i < MAX_SLOTS; ++i)
+        if (b->slot[i].used && b->h.active[i]) {
+            ++n;
+            c += b->slot[i].cells;
+        }
+    if (n_active) *n_active = n;
+    if (cells) *cells = c;
+    return EK_OK;
+}
+
+int ek_batch_destroy(ek_batch* b) {
+    if (!b) return EK_ERR_INVALID_ARG;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (int i = 0; i < MAX_SLOTS; ++i)
+        if (b->slot[i].used && b->slot[i].ctx) ek_destroy(b->slot[i].ctx);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->own_arena && b->arena) (void)hipFree(b->arena);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return EK_OK;
+}
+
+}  // extern "C"

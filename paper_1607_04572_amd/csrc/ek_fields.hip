@@ -218,10 +218,10 @@ __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T
 // Grid: tiles of TXW x TYW cells in x-y times z-chunks of ZC planes, flattened
 // and mapped with xcd_tile; each workgroup marches its ZC planes.
 template <typename T, bool DEV, int NS, int TXW, int TYW>
-__global__ __launch_bounds__(TXW* TYW) void k_ek(Sim<T> s, int ZC, int gx, int gy, int ntiles) {
+__device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int gx_, int ZC, int gx, int gy, int ntiles) {
     using SH = EKShared<T, NS, TXW, TYW>;
     __shared__ SH sh;
-    const int tile = xcd_tile(blockIdx.x, ntiles);
+    const int tile = xcd_tile(bx_, ntiles);
     const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
     const int x0 = bx * TXW, y0 = by * TYW, zbeg = bz * ZC;
     const T* __restrict__ rin = s.rho[s.cur];
@@ -290,12 +290,17 @@ __global__ __launch_bounds__(TXW* TYW) void k_ek(Sim<T> s, int ZC, int gx, int g
     }
 }
 
+template <typename T, bool DEV, int NS, int TXW, int TYW>
+__global__ __launch_bounds__(TXW* TYW) void k_ek(Sim<T> s, int ZC, int gx, int gy, int ntiles) {
+    ek_body<T, DEV, NS, TXW, TYW>(s, blockIdx.x, blockIdx.y, gridDim.x, ZC, gx, gy, ntiles);
+}
+
 // ---------------------------------------------------------------------------
 // LB
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
-__global__ __launch_bounds__(BT) void k_lb(Sim<T> s) {
-    long c = (long)blockIdx.x * BT + threadIdx.x;
+__device__ __forceinline__ void lb_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    long c = (long)bx_ * BT + threadIdx.x;
     if (c >= s.N) return;
     const int nx = s.nx, ny = s.ny, nz = s.nz;
     int x = (int)(c % nx);
@@ -386,15 +391,19 @@ __global__ __launch_bounds__(BT) void k_lb(Sim<T> s) {
     __builtin_nontemporal_store(uz, &s.u[2 * s.N + c]);
 }
 
+template <typename T, bool DEV>
+__global__ __launch_bounds__(BT) void k_lb(Sim<T> s) {
+    lb_body<T, DEV>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV, int NS>
 static void launch_ek_ns(const Sim<T>& s, hipStream_t st) {
-    constexpr int TXW = sizeof(T) == 4 ? 64 : 32, TYW = 4;
-    int gx = (s.nx + TXW - 1) / TXW, gy = (s.ny + TYW - 1) / TYW;
-    int ZC = 16;
-    int gz = (s.nz + ZC - 1) / ZC;
-    int nt = gx * gy * gz;
-    hipLaunchKernelGGL((k_ek<T, DEV, NS, TXW, TYW>), dim3(nt), dim3(TXW * TYW), 0, st, s, ZC, gx, gy, nt);
+    constexpr int TXW = EKTile<T>::TXW, TYW = EKTile<T>::TYW;
+    Grids<T> g = grids_of<T>(s);
+    int nt = g.n[KK_EK];
+    hipLaunchKernelGGL((k_ek<T, DEV, NS, TXW, TYW>), dim3(nt), dim3(TXW * TYW), 0, st, s, EKTile<T>::ZC, g.ek_gx,
+                       g.ek_gy, nt);
 }
 
 template <typename T>
@@ -412,6 +421,39 @@ template <typename T>
 void launch_lb(const Sim<T>& s, hipStream_t st) {
     constexpr bool DEV = sizeof(T) == 4;
     hipLaunchKernelGGL((k_lb<T, DEV>), dim3((unsigned)((s.N + BT - 1) / BT)), dim3(BT), 0, st, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batched EK and LB (FP32 tables)
+// ---------------------------------------------------------------------------
+constexpr int BATCH_FIELD_BLOCKS = 2048;
+
+template <int NS>
+__global__ __launch_bounds__(EKTile<float>::TXW* EKTile<float>::TYW) void kb_ek(const BatchTable* tab) {
+    constexpr int TXW = EKTile<float>::TXW, TYW = EKTile<float>::TYW, ZC = EKTile<float>::ZC;
+    batch_loop<KK_EK>(tab, [](const Sim<float>& s, int b) {
+        const int gx = (s.nx + TXW - 1) / TXW, gy = (s.ny + TYW - 1) / TYW;
+        const int nt = gx * gy * ((s.nz + ZC - 1) / ZC);
+        ek_body<float, true, NS, TXW, TYW>(s, b, 0, 0, ZC, gx, gy, nt);
+    });
+}
+
+__global__ __launch_bounds__(BT) void kb_lb(const BatchTable* tab) {
+    batch_loop<KK_LB>(tab, [](const Sim<float>& s, int b) { lb_body<float, true>(s, b, 0, 0); });
+}
+
+void launch_batch_ek(const BatchTable* tab, int ns, hipStream_t st) {
+    constexpr int NT = EKTile<float>::TXW * EKTile<float>::TYW;
+    switch (ns) {
+        case 1: hipLaunchKernelGGL(kb_ek<1>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
+        case 2: hipLaunchKernelGGL(kb_ek<2>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
+        case 3: hipLaunchKernelGGL(kb_ek<3>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
+        default: hipLaunchKernelGGL(kb_ek<4>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
+    }
+}
+
+void launch_batch_lb(const BatchTable* tab, hipStream_t st) {
+    hipLaunchKernelGGL(kb_lb, dim3(BATCH_FIELD_BLOCKS), dim3(BT), 0, st, tab);
 }
 
 template void launch_ek<float>(const Sim<float>&, hipStream_t);

@@ -127,6 +127,91 @@ struct Sim {
     int nchunk;               // workgroups per particle box in the particle kernels
 };
 
+// ---------------------------------------------------------------------------
+// Launch geometry shared by the single-simulation and batched launches
+// ---------------------------------------------------------------------------
+constexpr int FFT_THREADS = 256;
+constexpr int FFT_ELEMS = 16;   // pencil elements per thread of an FFT workgroup
+constexpr int POOL_BLOCKS = 64;
+
+// Pencils per workgroup in the x passes (P * n <= 2048).
+__host__ __device__ inline int fft_pencils_x(int n) {
+    int P = (FFT_THREADS * FFT_ELEMS / 2) / n;
+    return P < 1 ? 1 : P;
+}
+// Consecutive kx columns per workgroup in the y and z passes: 16 (FP32) or 8
+// (FP64) for coalesced 128-byte rows, fewer for long pencils (TX * n <= 4096).
+__host__ __device__ inline int fft_tile_kx(int n, int elem_bytes) {
+    int cap = (FFT_THREADS * FFT_ELEMS) / n;
+    int t = elem_bytes == 4 ? 16 : 8;
+    return t < cap ? t : cap;
+}
+// EK tiles: TXW x TYW cells per z-plane, ZC planes per workgroup.
+template <typename T> struct EKTile {
+    static constexpr int TXW = sizeof(T) == 4 ? 64 : 32, TYW = 4, ZC = 16;
+};
+
+// Workgroups of each kernel for one simulation.
+enum {
+    KK_MOVE, KK_PART, KK_PRED, KK_POOL, KK_FFTX, KK_FFTY, KK_FFTZ, KK_EK, KK_LB, KK_N
+};
+template <typename T>
+struct Grids {
+    int n[KK_N];
+    int ek_gx, ek_gy;
+};
+template <typename T, typename S>
+inline Grids<T> grids_of(const S& s) {
+    Grids<T> g;
+    g.n[KK_MOVE] = (s.np + 63) / 64;
+    g.n[KK_PART] = s.nchunk * s.np;
+    g.n[KK_PRED] = s.np;
+    g.n[KK_POOL] = s.np > 0 ? POOL_BLOCKS : 0;
+    int P = fft_pencils_x(s.nx);
+    g.n[KK_FFTX] = (s.ny * s.nz / 2 + P - 1) / P;
+    int TXy = fft_tile_kx(s.ny, sizeof(T)), TXz = fft_tile_kx(s.nz, sizeof(T));
+    g.n[KK_FFTY] = ((s.nxh + TXy - 1) / TXy) * s.nz;
+    g.n[KK_FFTZ] = ((s.nxh + TXz - 1) / TXz) * s.ny;
+    g.ek_gx = (s.nx + EKTile<T>::TXW - 1) / EKTile<T>::TXW;
+    g.ek_gy = (s.ny + EKTile<T>::TYW - 1) / EKTile<T>::TYW;
+    g.n[KK_EK] = g.ek_gx * g.ek_gy * ((s.nz + EKTile<T>::ZC - 1) / EKTile<T>::ZC);
+    g.n[KK_LB] = (int)((s.N + 255) / 256);
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Batched (serving) form: a table of FP32 simulations in device memory.  Each
+// batched kernel runs a fixed grid that walks, for its kernel kind, the
+// concatenated workgroups of all slots (start = prefix sums), so one fixed
+// launch sequence serves any mix and is captured once in a HIP graph.
+// ---------------------------------------------------------------------------
+constexpr int MAX_SLOTS = 64;
+struct BatchTable {
+    int nsims;                       // table entries in use (active or finishing)
+    int active[MAX_SLOTS];           // 1 while the slot still has steps to run
+    long long step[MAX_SLOTS];       // steps done
+    long long target[MAX_SLOTS];     // steps requested
+    int start[KK_N][MAX_SLOTS + 1];  // workgroup prefix sums per kernel kind
+    Sim<float> sims[MAX_SLOTS];
+};
+
+// Persistent loop over the workgroups of kernel kind KK: f(sim, local block).
+template <int KK, typename F>
+__device__ __forceinline__ void batch_loop(const BatchTable* tab, F&& f) {
+    const int n = tab->nsims;
+    const int total = tab->start[KK][n];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        int lo = 0, hi = n;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (tab->start[KK][mid] <= w) lo = mid;
+            else hi = mid;
+        }
+        if (tab->active[lo]) f(tab->sims[lo], w - tab->start[KK][lo]);
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ int wrapi(int i, int n) {
     i %= n;
     return i < 0 ? i + n : i;
@@ -157,6 +242,14 @@ template <typename T> void launch_forces(const Sim<T>& s, hipStream_t st);
 template <typename T> void fill(T* p, long n, T v, hipStream_t st);
 template <typename T> void launch_finish(const Sim<T>& s, hipStream_t st);
 template <typename T> void launch_diagnostics(const Sim<T>& s, hipStream_t st, double* out);
+// batched step pieces (FP32 tables)
+void launch_batch_particles_pre(const BatchTable* tab, hipStream_t st);
+void launch_batch_poisson(const BatchTable* tab, hipStream_t st);
+void launch_batch_ek(const BatchTable* tab, int ns, hipStream_t st);
+void launch_batch_lb(const BatchTable* tab, hipStream_t st);
+void launch_batch_hydro(const BatchTable* tab, hipStream_t st);
+void launch_batch_particles_post(const BatchTable* tab, hipStream_t st);
+void launch_batch_flip(BatchTable* tab, hipStream_t st);
 void launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
 
 }  // namespace ek

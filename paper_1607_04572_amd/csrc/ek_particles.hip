@@ -193,9 +193,9 @@ __device__ __forceinline__ double* partial_rec(const Sim<T>& s, int kind, int p,
 // Particle move (Sec. III.B) and box of this step.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_move(Sim<T> s, int init) {
+__device__ __forceinline__ void move_body(const Sim<T>& s, int bx_, int by_, int gx_, int init) {
 #pragma clang fp contract(off)
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int p = bx_ * blockDim.x + threadIdx.x;
     if (p >= s.np) return;
     PState& q = s.parts[p];
     double L[3] = {(double)s.nx, (double)s.ny, (double)s.nz};
@@ -240,6 +240,11 @@ __global__ void k_move(Sim<T> s, int init) {
     q.ncov = q.nvac = q.npool = q.nflag = 0;
 }
 
+template <typename T>
+__global__ void k_move(Sim<T> s, int init) {
+    move_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, init);
+}
+
 // ---------------------------------------------------------------------------
 // Coverage of the cells of each box: flag (centre inside, Fig. 1), owner
 // (lowest particle index), Psi = min(1, sum_p Psi_p), particle charge rho_b
@@ -248,13 +253,13 @@ __global__ void k_move(Sim<T> s, int init) {
 // loops are wavefront-uniform so that cut cells can be resolved cooperatively.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(PT) void k_geometry(Sim<T> s, int init) {
+__device__ __forceinline__ void geometry_body(const Sim<T>& s, int bx_, int by_, int gx_, int init) {
 #pragma clang fp contract(off)
-    int p = blockIdx.y;
+    int p = by_;
     const PState& me = s.parts[p];
     const int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int base = blockIdx.x * PT + wave * 64; base < ncell; base += gridDim.x * PT) {
+    for (int base = bx_ * PT + wave * 64; base < ncell; base += gx_ * PT) {
         int t = base + lane;
         int x = 0, y = 0, z = 0;
         bool active = t < ncell;
@@ -303,6 +308,11 @@ __global__ __launch_bounds__(PT) void k_geometry(Sim<T> s, int init) {
 }
 
 template <typename T>
+__global__ __launch_bounds__(PT) void k_geometry(Sim<T> s, int init) {
+    geometry_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, init);
+}
+
+template <typename T>
 __device__ __forceinline__ double pop_abs(const Sim<T>& s, const T* f, int i, long c, double wi) {
     return sizeof(T) == 4 ? wi + (double)f[(long)i * s.N + c] : (double)f[(long)i * s.N + c];
 }
@@ -322,9 +332,9 @@ __device__ __forceinline__ double rho_abs(const Sim<T>& s, const T* r, int k, lo
 // covered cells that have no stable-fluid neighbour at all (global pool).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
+__device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_, int gx_) {
 #pragma clang fp contract(off)
-    int p = blockIdx.y;
+    int p = by_;
     const PState& me = s.parts[p];
     int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     T* f = s.f[s.cur];
@@ -332,7 +342,7 @@ __global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
     // 0-2 Fc, 3-5 Tc, 6..6+MAXS pool, then counts
     double acc[6 + MAXS + 5];
     for (int k = 0; k < 6 + MAXS + 5; ++k) acc[k] = 0.0;
-    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += s.nchunk * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += s.nchunk * PT) {
         int x, y, z;
         box_cell(s, me, t, x, y, z);
         long c = cidx(s, x, y, z);
@@ -415,15 +425,20 @@ __global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
     }
     block_sum(acc);
     if (threadIdx.x == 0) {
-        double* out = partial_rec(s, PART_BOUNDARY, p, blockIdx.x);
+        double* out = partial_rec(s, PART_BOUNDARY, p, bx_);
         for (int k = 0; k < 6 + MAXS + 5; ++k) out[k] = acc[k];
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
+    boundary_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // Chunk partials of k_boundary -> particle record, summed in chunk order.
 template <typename T>
-__global__ void k_boundary_reduce(Sim<T> s) {
-    int p = blockIdx.x, k = threadIdx.x;
+__device__ __forceinline__ void boundary_reduce_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    int p = bx_, k = threadIdx.x;
     if (k >= 6 + MAXS + 5) return;
     double v = 0.0;
     for (int c = 0; c < s.nchunk; ++c) v += partial_rec(s, PART_BOUNDARY, p, c)[k];
@@ -438,6 +453,11 @@ __global__ void k_boundary_reduce(Sim<T> s) {
     else me.nflag = (int)v;
 }
 
+template <typename T>
+__global__ void k_boundary_reduce(Sim<T> s) {
+    boundary_reduce_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Solute expel (Sec. III.D.1), gather form in FP64: every stable-fluid cell
 // collects, from each covered neighbour c, rho(c)/n19(c) if it is one of c's
@@ -445,12 +465,12 @@ __global__ void k_boundary_reduce(Sim<T> s) {
 // the D3Q27 neighbourhood.  Covered cells are emptied by k_boundary_post.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(PT) void k_expel(Sim<T> s) {
-    int p = blockIdx.y;
+__device__ __forceinline__ void expel_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    int p = by_;
     const PState& me = s.parts[p];
     int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     T* rho = s.rho[s.cur];
-    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += gx_ * PT) {
         int x, y, z;
         box_cell(s, me, t, x, y, z);
         long n = cidx(s, x, y, z);
@@ -490,15 +510,20 @@ __global__ __launch_bounds__(PT) void k_expel(Sim<T> s) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(PT) void k_expel(Sim<T> s) {
+    expel_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // Covered cells lose their solute; in the uniform charge mode each owned cell
 // receives Z / n_b of its particle's charge.
 template <typename T>
-__global__ __launch_bounds__(PT) void k_boundary_post(Sim<T> s) {
-    int p = blockIdx.y;
+__device__ __forceinline__ void boundary_post_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    int p = by_;
     const PState& me = s.parts[p];
     int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     T* rho = s.rho[s.cur];
-    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += gx_ * PT) {
         int x, y, z;
         box_cell(s, me, t, x, y, z);
         long c = cidx(s, x, y, z);
@@ -513,11 +538,16 @@ __global__ __launch_bounds__(PT) void k_boundary_post(Sim<T> s) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(PT) void k_boundary_post(Sim<T> s) {
+    boundary_post_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // Solute of covered cells with no stable-fluid neighbour in their whole
 // 26-neighbourhood is spread uniformly over all stable-fluid cells.  Exits at
 // once when there is none (the usual case).
 template <typename T>
-__global__ __launch_bounds__(PT) void k_pool(Sim<T> s) {
+__device__ __forceinline__ void pool_body(const Sim<T>& s, int bx_, int by_, int gx_) {
     double pool[MAXS] = {0.0, 0.0, 0.0, 0.0};
     long nflag = 0;
     bool any = false;
@@ -531,7 +561,7 @@ __global__ __launch_bounds__(PT) void k_pool(Sim<T> s) {
     long nS = s.N - s.n_wall - nflag;
     if (nS <= 0) return;
     T* rho = s.rho[s.cur];
-    for (long c = (long)blockIdx.x * PT + threadIdx.x; c < s.N; c += (long)gridDim.x * PT) {
+    for (long c = (long)bx_ * PT + threadIdx.x; c < s.N; c += (long)gx_ * PT) {
         if (!stable(s.flag[c])) continue;
         for (int k = 0; k < s.ns; ++k) {
             double v = rho_abs(s, rho, k, c) + pool[k] / (double)nS;
@@ -540,11 +570,16 @@ __global__ __launch_bounds__(PT) void k_pool(Sim<T> s) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(PT) void k_pool(Sim<T> s) {
+    pool_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // Initial density rule: boundary cells empty; partial-volume fluid cells keep
 // (1 - Psi) of the given concentration.  Whole grid, once.
 template <typename T>
-__global__ __launch_bounds__(PT) void k_init_density(Sim<T> s) {
-    long c = (long)blockIdx.x * PT + threadIdx.x;
+__device__ __forceinline__ void init_density_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    long c = (long)bx_ * PT + threadIdx.x;
     if (c >= s.N) return;
     uint8_t fl = s.flag[c];
     double psi = s.psi[c];
@@ -557,6 +592,11 @@ __global__ __launch_bounds__(PT) void k_init_density(Sim<T> s) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(PT) void k_init_density(Sim<T> s) {
+    init_density_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Forces on the particles.
 // Momentum exchange (Sec. III.B, Eq. force): for each link from a fluid cell
@@ -565,14 +605,14 @@ __global__ __launch_bounds__(PT) void k_init_density(Sim<T> s) {
 // Electrostatic: F = kT sum rho_b,p (E - grad phi), central differences.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(PT) void k_hydro_force(Sim<T> s) {
+__device__ __forceinline__ void hydro_force_body(const Sim<T>& s, int bx_, int by_, int gx_) {
 #pragma clang fp contract(off)
-    int p = blockIdx.y;
+    int p = by_;
     const PState& me = s.parts[p];
     int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     const T* f = s.f[s.cur];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += s.nchunk * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += s.nchunk * PT) {
         int x, y, z;
         box_cell(s, me, t, x, y, z);
         long b = cidx(s, x, y, z);
@@ -603,20 +643,25 @@ __global__ __launch_bounds__(PT) void k_hydro_force(Sim<T> s) {
     }
     block_sum(acc);
     if (threadIdx.x == 0) {
-        double* out = partial_rec(s, PART_HYDRO, p, blockIdx.x);
+        double* out = partial_rec(s, PART_HYDRO, p, bx_);
         for (int k = 0; k < 6; ++k) out[k] = acc[k];
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(PT) void k_el_force(Sim<T> s) {
+__global__ __launch_bounds__(PT) void k_hydro_force(Sim<T> s) {
+    hydro_force_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__device__ __forceinline__ void el_force_body(const Sim<T>& s, int bx_, int by_, int gx_) {
 #pragma clang fp contract(off)
-    int p = blockIdx.y;
+    int p = by_;
     const PState& me = s.parts[p];
     const int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     const double R2 = me.R * me.R;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int base = blockIdx.x * PT; base < ncell; base += s.nchunk * PT) {
+    for (int base = bx_ * PT; base < ncell; base += s.nchunk * PT) {
         int t = base + threadIdx.x;
         int x = 0, y = 0, z = 0;
         bool active = t < ncell;
@@ -654,18 +699,23 @@ __global__ __launch_bounds__(PT) void k_el_force(Sim<T> s) {
     }
     block_sum(acc);
     if (threadIdx.x == 0) {
-        double* out = partial_rec(s, PART_EL, p, blockIdx.x);
+        double* out = partial_rec(s, PART_EL, p, bx_);
         for (int k = 0; k < 6; ++k) out[k] = acc[k];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(PT) void k_el_force(Sim<T> s) {
+    el_force_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // Total force of the step and the closing half kick of velocity Verlet.  One
 // workgroup per particle: lane k < 12 sums component k of the hydrodynamic and
 // electrostatic chunk partials in chunk order (deterministic).
 template <typename T>
-__global__ void k_finish(Sim<T> s) {
+__device__ __forceinline__ void finish_body(const Sim<T>& s, int bx_, int by_, int gx_) {
 #pragma clang fp contract(off)
-    const int p = blockIdx.x, k = threadIdx.x;
+    const int p = bx_, k = threadIdx.x;
     __shared__ double sum[12];
     if (k < 12) {
         const int kind = k < 6 ? PART_HYDRO : PART_EL;
@@ -701,6 +751,11 @@ __global__ void k_finish(Sim<T> s) {
     }
 }
 
+template <typename T>
+__global__ void k_finish(Sim<T> s) {
+    finish_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Simple scheme (Sec. III.D.1, Eqs. refill and refill-neighbours): a vacated
 // cell v with N_f stable-fluid D3Q19 neighbours receives
@@ -721,12 +776,12 @@ __device__ __forceinline__ int stable19(const Sim<T>& s, int x, int y, int z) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(PT) void k_refill_vacated(Sim<T> s) {
-    int p = blockIdx.y;
+__device__ __forceinline__ void refill_vacated_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    int p = by_;
     const PState& me = s.parts[p];
     int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     T* rho = s.rho[s.cur];
-    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += gx_ * PT) {
         int x, y, z;
         box_cell(s, me, t, x, y, z);
         long v = cidx(s, x, y, z);
@@ -747,12 +802,17 @@ __global__ __launch_bounds__(PT) void k_refill_vacated(Sim<T> s) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(PT) void k_refill_stable(Sim<T> s) {
-    int p = blockIdx.y;
+__global__ __launch_bounds__(PT) void k_refill_vacated(Sim<T> s) {
+    refill_vacated_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__device__ __forceinline__ void refill_stable_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    int p = by_;
     const PState& me = s.parts[p];
     int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
     T* rho = s.rho[s.cur];
-    for (int t = blockIdx.x * PT + threadIdx.x; t < ncell; t += gridDim.x * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += gx_ * PT) {
         int x, y, z;
         box_cell(s, me, t, x, y, z);
         long n = cidx(s, x, y, z);
@@ -787,10 +847,14 @@ __global__ __launch_bounds__(PT) void k_refill_stable(Sim<T> s) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(PT) void k_refill_stable(Sim<T> s) {
+    refill_stable_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static int box_chunks(int box_max) { return (box_max + PT - 1) / PT < 64 ? (box_max + PT - 1) / PT : 64; }
 static_assert(6 + MAXS + 5 <= PSTRIDE, "partial record too small");
 
 template <typename T>
@@ -802,7 +866,7 @@ void launch_move(const Sim<T>& s, hipStream_t st, int init) {
 template <typename T>
 void launch_geometry(const Sim<T>& s, hipStream_t st, int init) {
     if (s.np == 0) return;
-    hipLaunchKernelGGL(k_geometry<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s, init);
+    hipLaunchKernelGGL(k_geometry<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s, init);
 }
 
 template <typename T>
@@ -810,16 +874,16 @@ void launch_boundary(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
     hipLaunchKernelGGL(k_boundary<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
     hipLaunchKernelGGL(k_boundary_reduce<T>, dim3(s.np), dim3(64), 0, st, s);
-    hipLaunchKernelGGL(k_expel<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
-    hipLaunchKernelGGL(k_boundary_post<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
-    hipLaunchKernelGGL(k_pool<T>, dim3(256), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_expel<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_boundary_post<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_pool<T>, dim3(POOL_BLOCKS), dim3(PT), 0, st, s);
 }
 
 template <typename T>
 void launch_refill(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
-    hipLaunchKernelGGL(k_refill_vacated<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
-    hipLaunchKernelGGL(k_refill_stable<T>, dim3(box_chunks(s.box_max), s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_refill_vacated<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_refill_stable<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
 }
 
 template <typename T>
@@ -843,6 +907,88 @@ template <typename T>
 void launch_finish(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
     hipLaunchKernelGGL(k_finish<T>, dim3(s.np), dim3(64), 0, st, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batched particle kernels (persistent grids over a BatchTable)
+// ---------------------------------------------------------------------------
+constexpr int BATCH_PART_BLOCKS = 1024;
+constexpr int BATCH_SMALL_BLOCKS = 256;
+
+__global__ void kb_move(const BatchTable* tab) {
+    batch_loop<KK_MOVE>(tab, [](const Sim<float>& s, int b) { move_body<float>(s, b, 0, 0, 0); });
+}
+__global__ __launch_bounds__(PT) void kb_geometry(const BatchTable* tab) {
+    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+        geometry_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk, 0);
+    });
+}
+__global__ __launch_bounds__(PT) void kb_boundary(const BatchTable* tab) {
+    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+        boundary_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
+    });
+}
+__global__ void kb_boundary_reduce(const BatchTable* tab) {
+    batch_loop<KK_PRED>(tab, [](const Sim<float>& s, int b) { boundary_reduce_body<float>(s, b, 0, 0); });
+}
+__global__ __launch_bounds__(PT) void kb_expel(const BatchTable* tab) {
+    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+        expel_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
+    });
+}
+__global__ __launch_bounds__(PT) void kb_boundary_post(const BatchTable* tab) {
+    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+        boundary_post_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
+    });
+}
+__global__ __launch_bounds__(PT) void kb_pool(const BatchTable* tab) {
+    batch_loop<KK_POOL>(tab, [](const Sim<float>& s, int b) { pool_body<float>(s, b, 0, POOL_BLOCKS); });
+}
+__global__ __launch_bounds__(PT) void kb_refill_vacated(const BatchTable* tab) {
+    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+        if (!s.pv) refill_vacated_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
+    });
+}
+__global__ __launch_bounds__(PT) void kb_refill_stable(const BatchTable* tab) {
+    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+        if (!s.pv) refill_stable_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
+    });
+}
+__global__ __launch_bounds__(PT) void kb_hydro_force(const BatchTable* tab) {
+    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+        hydro_force_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
+    });
+}
+__global__ __launch_bounds__(PT) void kb_el_force(const BatchTable* tab) {
+    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+        el_force_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
+    });
+}
+__global__ void kb_finish(const BatchTable* tab) {
+    batch_loop<KK_PRED>(tab, [](const Sim<float>& s, int b) { finish_body<float>(s, b, 0, 0); });
+}
+
+void launch_batch_particles_pre(const BatchTable* tab, hipStream_t st) {
+    hipLaunchKernelGGL(kb_move, dim3(BATCH_SMALL_BLOCKS), dim3(64), 0, st, tab);
+    hipLaunchKernelGGL(kb_geometry, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_boundary, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_boundary_reduce, dim3(BATCH_SMALL_BLOCKS), dim3(64), 0, st, tab);
+    hipLaunchKernelGGL(kb_expel, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_boundary_post, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_pool, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_refill_vacated, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_refill_stable, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+}
+
+void launch_batch_particles_post(const BatchTable* tab, hipStream_t st) {
+    hipLaunchKernelGGL(kb_el_force, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_finish, dim3(BATCH_SMALL_BLOCKS), dim3(64), 0, st, tab);
+}
+
+// the momentum exchange reads the populations before the LB overwrites the
+// other buffer; it is launched with the post-Poisson group by the host
+void launch_batch_hydro(const BatchTable* tab, hipStream_t st) {
+    hipLaunchKernelGGL(kb_hydro_force, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
 }
 
 #define EK_INST(T)                                                     \

@@ -89,8 +89,8 @@ __device__ __forceinline__ void dft_small(cpx<T> (&v)[R]) {
 // the same buffer (so one LDS buffer suffices).  Butterfly b of pencil p, with
 // j = b mod (n/R) and k = j mod Ns, reads indices j + r n/R, multiplies by
 // e^{-+2 pi i k r / (Ns R)} and writes (j div Ns) Ns R + k + r Ns.
-constexpr int FT = 256;    // threads per FFT workgroup
-constexpr int FE = 16;     // pencil elements per thread (P * n <= FT * FE)
+constexpr int FT = FFT_THREADS;  // threads per FFT workgroup
+constexpr int FE = FFT_ELEMS;    // pencil elements per thread (P * n <= FT * FE)
 
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, const cpx<T>* __restrict__ tw) {
@@ -162,12 +162,12 @@ __device__ __forceinline__ void fft_lds(cpx<T>* a, int n, int P, int ld, const c
 // Work item: a pair of rows (y, y+1) at one z.  P pairs per workgroup.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(FT) void k_fft_x_fwd(Sim<T> s, int P) {
+__device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_, int gx_, int P) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
     const int n = s.nx, ld = n + 1;
     const int npairs = s.ny * s.nz / 2;
-    const int pair0 = blockIdx.x * P;
+    const int pair0 = bx_ * P;
     const T* rho = s.rho[s.cur];
     for (int t = threadIdx.x; t < P * n; t += FT) {
         int pen = t / n, x = t - pen * n;
@@ -206,17 +206,22 @@ __global__ __launch_bounds__(FT) void k_fft_x_fwd(Sim<T> s, int P) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(FT) void k_fft_x_fwd(Sim<T> s, int P) {
+    fft_x_fwd_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, P);
+}
+
 // ---------------------------------------------------------------------------
 // Pass X' (inverse): two half spectra -> one complex sequence -> two real rows.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(FT) void k_fft_x_inv(Sim<T> s, int P) {
+__device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_, int gx_, int P) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
     const int n = s.nx, ld = n + 1;
     const int nh = s.nxh;
     const int npairs = s.ny * s.nz / 2;
-    const int pair0 = blockIdx.x * P;
+    const int pair0 = bx_ * P;
     const cpx<T>* S = reinterpret_cast<const cpx<T>*>(s.spec);
     for (int t = threadIdx.x; t < P * n; t += FT) {
         int pen = t / n, k = t - pen * n;
@@ -247,17 +252,22 @@ __global__ __launch_bounds__(FT) void k_fft_x_inv(Sim<T> s, int P) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(FT) void k_fft_x_inv(Sim<T> s, int P) {
+    fft_x_inv_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, P);
+}
+
 // ---------------------------------------------------------------------------
 // Pass Y (forward or inverse): pencils along y, TX consecutive kx per group.
 // ---------------------------------------------------------------------------
 template <typename T, bool INV>
-__global__ __launch_bounds__(FT) void k_fft_y(Sim<T> s, int TX) {
+__device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int by_, int gx_, int TX) {
     extern __shared__ unsigned char smem_raw[];
     const int n = s.ny, nh = s.nxh, ld = n + 1;
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
     int tiles = (nh + TX - 1) / TX;
-    int z = blockIdx.x / tiles;
-    int kx0 = (blockIdx.x - z * tiles) * TX;
+    int z = bx_ / tiles;
+    int kx0 = (bx_ - z * tiles) * TX;
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec) + (long)z * n * nh;
     for (int t = threadIdx.x; t < TX * n; t += FT) {
         int y = t / TX, i = t - y * TX;
@@ -273,17 +283,22 @@ __global__ __launch_bounds__(FT) void k_fft_y(Sim<T> s, int TX) {
     }
 }
 
+template <typename T, bool INV>
+__global__ __launch_bounds__(FT) void k_fft_y(Sim<T> s, int TX) {
+    fft_y_body<T, INV>(s, blockIdx.x, blockIdx.y, gridDim.x, TX);
+}
+
 // ---------------------------------------------------------------------------
 // Pass Z: forward FFT along z, multiply by the Green's function, inverse FFT.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(FT) void k_fft_z_green(Sim<T> s, int TX) {
+__device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int by_, int gx_, int TX) {
     extern __shared__ unsigned char smem_raw[];
     const int n = s.nz, nh = s.nxh, ny = s.ny, ld = n + 1;
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
     int tiles = (nh + TX - 1) / TX;
-    int ky = blockIdx.x / tiles;
-    int kx0 = (blockIdx.x - ky * tiles) * TX;
+    int ky = bx_ / tiles;
+    int kx0 = (bx_ - ky * tiles) * TX;
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
     const long zstride = (long)ny * nh;
     for (int t = threadIdx.x; t < TX * n; t += FT) {
@@ -314,39 +329,79 @@ __global__ __launch_bounds__(FT) void k_fft_z_green(Sim<T> s, int TX) {
     }
 }
 
-// Pencils per workgroup in the x passes: P * n <= FT * FE / 2.
 template <typename T>
-static int pencils_x(int n) {
-    int P = (FT * FE / 2) / n;
-    return P < 1 ? 1 : P;
-}
-
-// Consecutive kx columns per workgroup in the y and z passes: 16 (FP32) or 8
-// (FP64) for coalesced 128-byte rows, fewer for long pencils so that
-// TX * n <= FT * FE (registers of the in-place stages).
-template <typename T>
-static int tile_kx(int n) {
-    int cap = (FT * FE) / n;
-    int t = sizeof(T) == 4 ? 16 : 8;
-    return t < cap ? t : cap;
+__global__ __launch_bounds__(FT) void k_fft_z_green(Sim<T> s, int TX) {
+    fft_z_green_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, TX);
 }
 
 template <typename T>
 void launch_charge_poisson(const Sim<T>& s, hipStream_t st) {
     const size_t cs = sizeof(cpx<T>);
-    int P = pencils_x<T>(s.nx);
-    int npairs = s.ny * s.nz / 2;
-    int gx = (npairs + P - 1) / P;
+    Grids<T> g = grids_of<T>(s);
+    int P = fft_pencils_x(s.nx);
     size_t shx = (size_t)P * (s.nx + 1) * cs;
-    hipLaunchKernelGGL(k_fft_x_fwd<T>, dim3(gx), dim3(FT), shx, st, s, P);
-    int TXy = tile_kx<T>(s.ny), TXz = tile_kx<T>(s.nz);
-    int tiles_y = (s.nxh + TXy - 1) / TXy, tiles_z = (s.nxh + TXz - 1) / TXz;
+    hipLaunchKernelGGL(k_fft_x_fwd<T>, dim3(g.n[KK_FFTX]), dim3(FT), shx, st, s, P);
+    int TXy = fft_tile_kx(s.ny, sizeof(T)), TXz = fft_tile_kx(s.nz, sizeof(T));
     size_t shy = (size_t)TXy * (s.ny + 1) * cs;
-    hipLaunchKernelGGL((k_fft_y<T, false>), dim3(tiles_y * s.nz), dim3(FT), shy, st, s, TXy);
+    hipLaunchKernelGGL((k_fft_y<T, false>), dim3(g.n[KK_FFTY]), dim3(FT), shy, st, s, TXy);
     size_t shz = (size_t)TXz * (s.nz + 1) * cs;
-    hipLaunchKernelGGL(k_fft_z_green<T>, dim3(tiles_z * s.ny), dim3(FT), shz, st, s, TXz);
-    hipLaunchKernelGGL((k_fft_y<T, true>), dim3(tiles_y * s.nz), dim3(FT), shy, st, s, TXy);
-    hipLaunchKernelGGL(k_fft_x_inv<T>, dim3(gx), dim3(FT), shx, st, s, P);
+    hipLaunchKernelGGL(k_fft_z_green<T>, dim3(g.n[KK_FFTZ]), dim3(FT), shz, st, s, TXz);
+    hipLaunchKernelGGL((k_fft_y<T, true>), dim3(g.n[KK_FFTY]), dim3(FT), shy, st, s, TXy);
+    hipLaunchKernelGGL(k_fft_x_inv<T>, dim3(g.n[KK_FFTX]), dim3(FT), shx, st, s, P);
+}
+
+// ---------------------------------------------------------------------------
+// Batched passes (FP32 tables): P and TX are derived per simulation; the LDS
+// size is the largest any allowed edge needs.
+// ---------------------------------------------------------------------------
+constexpr int BATCH_FFT_BLOCKS = 2048;
+
+static size_t batch_lds_x() {
+    size_t m = 0;
+    for (int n = 8; n <= MAX_FFT; n += 2) {
+        size_t v = (size_t)fft_pencils_x(n) * (n + 1) * sizeof(cpx<float>);
+        m = v > m ? v : m;
+    }
+    return m;
+}
+static size_t batch_lds_yz() {
+    size_t m = 0;
+    for (int n = 8; n <= MAX_FFT; n += 2) {
+        size_t v = (size_t)fft_tile_kx(n, 4) * (n + 1) * sizeof(cpx<float>);
+        m = v > m ? v : m;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(FT) void kb_fft_x_fwd(const BatchTable* tab) {
+    batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) {
+        fft_x_fwd_body<float>(s, b, 0, 0, fft_pencils_x(s.nx));
+    });
+}
+__global__ __launch_bounds__(FT) void kb_fft_x_inv(const BatchTable* tab) {
+    batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) {
+        fft_x_inv_body<float>(s, b, 0, 0, fft_pencils_x(s.nx));
+    });
+}
+template <bool INV>
+__global__ __launch_bounds__(FT) void kb_fft_y(const BatchTable* tab) {
+    batch_loop<KK_FFTY>(tab, [](const Sim<float>& s, int b) {
+        fft_y_body<float, INV>(s, b, 0, 0, fft_tile_kx(s.ny, 4));
+    });
+}
+__global__ __launch_bounds__(FT) void kb_fft_z_green(const BatchTable* tab) {
+    batch_loop<KK_FFTZ>(tab, [](const Sim<float>& s, int b) {
+        fft_z_green_body<float>(s, b, 0, 0, fft_tile_kx(s.nz, 4));
+    });
+}
+
+void launch_batch_poisson(const BatchTable* tab, hipStream_t st) {
+    size_t lx = batch_lds_x(), lyz = batch_lds_yz();
+    hipLaunchKernelGGL(kb_fft_x_fwd, dim3(BATCH_FFT_BLOCKS), dim3(FT), lx, st, tab);
+    hipLaunchKernelGGL(kb_fft_y<false>, dim3(BATCH_FFT_BLOCKS), dim3(FT), lyz, st, tab);
+    hipLaunchKernelGGL(kb_fft_z_green, dim3(BATCH_FFT_BLOCKS), dim3(FT), lyz, st, tab);
+    hipLaunchKernelGGL(kb_fft_y<true>, dim3(BATCH_FFT_BLOCKS), dim3(FT), lyz, st, tab);
+    hipLaunchKernelGGL(kb_fft_x_inv, dim3(BATCH_FFT_BLOCKS), dim3(FT), lx, st, tab);
 }
 
 template void launch_charge_poisson<float>(const Sim<float>&, hipStream_t);

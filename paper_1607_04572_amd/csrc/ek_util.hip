@@ -120,4 +120,19 @@ void launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(UT), 0, st, (float4*)dst, (const float4*)src, n16);
 }
 
+// End of a batched step: every active slot toggles its ping-pong buffers and
+// counts the step; a slot that reached its requested steps stops.
+__global__ void k_batch_flip(BatchTable* tab) {
+    int i = threadIdx.x;
+    if (i >= tab->nsims || !tab->active[i]) return;
+    tab->sims[i].cur ^= 1;
+    long long st = tab->step[i] + 1;
+    tab->step[i] = st;
+    if (st >= tab->target[i]) tab->active[i] = 0;
+}
+
+void launch_batch_flip(BatchTable* tab, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_flip, dim3(1), dim3(MAX_SLOTS), 0, st, tab);
+}
+
 }  // namespace ek

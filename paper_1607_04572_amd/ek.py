@@ -59,6 +59,11 @@ class ek_particle(C.Structure):
                 ("mode", C.c_int), ("n_boundary", C.c_int)]
 
 
+class ek_sphere(C.Structure):
+    _fields_ = [("x", C.c_double * 3), ("v", C.c_double * 3), ("radius", C.c_double), ("charge", C.c_double),
+                ("mass", C.c_double), ("mode", C.c_int)]
+
+
 class ek_diag(C.Structure):
     _fields_ = [("step", C.c_longlong), ("species_total", C.c_double * MAX_SPECIES),
                 ("solute_charge", C.c_double), ("particle_charge", C.c_double),
@@ -73,6 +78,8 @@ SYMBOLS = ["ek_query_footprint", "ek_create", "ek_add_sphere", "ek_set_static_bo
            "ek_get_state", "ek_set_state", "ek_profile_stages", "ek_copy_probe", "ek_synchronize",
            "ek_destroy", "ek_strerror"]
 STAGES = ["move", "geometry", "boundary", "poisson", "ek", "hydro", "lb", "forces", "finish"]
+BATCH_SYMBOLS = ["ek_batch_create", "ek_batch_admit", "ek_batch_step", "ek_batch_poll", "ek_batch_collect",
+                 "ek_batch_get_fields", "ek_batch_active", "ek_batch_destroy"]
 
 _LIB = None
 
@@ -104,6 +111,17 @@ def lib():
         L.ek_copy_probe.argtypes = [vp, vp, C.c_size_t, vp]
         L.ek_synchronize.argtypes = [vp]
         L.ek_destroy.argtypes = [vp]
+        L.ek_batch_create.argtypes = [C.c_size_t, C.c_int, vp, vp, P(vp)]
+        L.ek_batch_admit.argtypes = [vp, P(ek_params), P(ek_sphere), C.c_int, P(C.c_double), C.c_longlong,
+                                     P(C.c_int)]
+        L.ek_batch_step.argtypes = [vp, C.c_int]
+        L.ek_batch_poll.argtypes = [vp, P(C.c_int), C.c_int, P(C.c_int)]
+        L.ek_batch_collect.argtypes = [vp, C.c_int, P(ek_particle), C.c_int, P(ek_diag)]
+        L.ek_batch_get_fields.argtypes = [vp, C.c_int, C.c_int, vp, C.c_size_t]
+        L.ek_batch_active.argtypes = [vp, P(C.c_int), P(C.c_longlong)]
+        L.ek_batch_destroy.argtypes = [vp]
+        for sname in BATCH_SYMBOLS:
+            getattr(L, sname).restype = C.c_int
         L.ek_strerror.argtypes = [C.c_int]
         L.ek_strerror.restype = C.c_char_p
         for s in SYMBOLS:
@@ -225,6 +243,134 @@ def ek_synchronize(ctx):
 
 def ek_destroy(ctx):
     _check(lib().ek_destroy(ctx), "ek_destroy")
+
+
+# -- serving form ----------------------------------------------------------------
+def _particles_to_dicts(arr, n):
+    return [{f: (np.array(getattr(arr[k], f)[:]) if isinstance(getattr(arr[k], f), C.Array) else getattr(arr[k], f))
+             for f, _ in ek_particle._fields_} for k in range(n)]
+
+
+def ek_batch_create(arena_bytes: int, n_species: int, stream: int = 0, arena: int = 0):
+    h = C.c_void_p()
+    _check(lib().ek_batch_create(arena_bytes, n_species, C.c_void_p(stream or None), C.c_void_p(arena or None),
+                                 C.byref(h)), "ek_batch_create")
+    return h
+
+
+def ek_batch_admit(b, p: ek_params, spheres: list, initial_density, n_steps: int) -> int:
+    arr = (ek_sphere * max(1, len(spheres)))()
+    for k, sp in enumerate(spheres):
+        for d in range(3):
+            arr[k].x[d] = sp.x[d]
+            arr[k].v[d] = sp.v[d]
+        arr[k].radius, arr[k].charge, arr[k].mass, arr[k].mode = sp.R, sp.Z, sp.M, sp.mode
+    rho = None
+    if initial_density is not None:
+        rho = np.ascontiguousarray(initial_density, dtype=np.float64).reshape(-1)
+    slot = C.c_int(-1)
+    _check(lib().ek_batch_admit(b, C.byref(p), arr, len(spheres), None if rho is None else _dptr(rho),
+                                int(n_steps), C.byref(slot)), "ek_batch_admit")
+    return slot.value
+
+
+def ek_batch_step(b, k: int):
+    _check(lib().ek_batch_step(b, int(k)), "ek_batch_step")
+
+
+def ek_batch_poll(b, cap: int = 64) -> list:
+    out = (C.c_int * cap)()
+    n = C.c_int(0)
+    _check(lib().ek_batch_poll(b, out, cap, C.byref(n)), "ek_batch_poll")
+    return [out[i] for i in range(n.value)]
+
+
+def ek_batch_collect(b, slot: int, n: int):
+    arr = (ek_particle * max(1, n))()
+    d = ek_diag()
+    _check(lib().ek_batch_collect(b, int(slot), arr, int(n), C.byref(d)), "ek_batch_collect")
+    diag = {f: (np.array(getattr(d, f)[:]) if isinstance(getattr(d, f), C.Array) else getattr(d, f))
+            for f, _ in ek_diag._fields_}
+    return _particles_to_dicts(arr, n), diag
+
+
+def ek_batch_get_fields(b, slot: int, field, n_cells: int, n_species: int = 1) -> np.ndarray:
+    f = FIELDS.get(field, field)
+    if f == FIELDS["flag"]:
+        out = np.empty(n_cells, np.uint8)
+    elif f == FIELDS["owner"]:
+        out = np.empty(n_cells, np.int32)
+    else:
+        mult = {0: n_species, 2: 3, 4: 3, 8: 19}.get(f, 1)
+        out = np.empty(mult * n_cells, np.float64)
+    _check(lib().ek_batch_get_fields(b, int(slot), f, out.ctypes.data, out.nbytes), "ek_batch_get_fields")
+    return out
+
+
+def ek_batch_active(b):
+    n = C.c_int(0)
+    cells = C.c_longlong(0)
+    _check(lib().ek_batch_active(b, C.byref(n), C.byref(cells)), "ek_batch_active")
+    return n.value, cells.value
+
+
+def ek_batch_destroy(b):
+    _check(lib().ek_batch_destroy(b), "ek_batch_destroy")
+
+
+class EkBatch:
+    """A batch of FP32 simulations in one arena on cuda:0 (arena and stream
+    from PyTorch)."""
+
+    def __init__(self, arena_bytes: int, n_species: int = 2, use_torch: bool = True):
+        self._arena = None
+        self._stream = None
+        stream = arena = 0
+        if use_torch:
+            import torch
+            dev = torch.device("cuda", 0)
+            self._stream = torch.cuda.Stream(device=dev)
+            self._arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+            torch.cuda.synchronize(dev)
+            stream, arena = self._stream.cuda_stream, self._arena.data_ptr()
+        self.ns = n_species
+        self.h = ek_batch_create(arena_bytes, n_species, stream, arena)
+        self.meta = {}
+
+    def admit(self, w, initial_density=None, n_steps=None) -> int:
+        p = params_from_workload(w, max_particles=max(1, len(w.spheres)))
+        slot = ek_batch_admit(self.h, p, w.spheres, initial_density, w.steps if n_steps is None else n_steps)
+        self.meta[slot] = w
+        return slot
+
+    def step(self, k: int):
+        ek_batch_step(self.h, k)
+
+    def poll(self) -> list:
+        return ek_batch_poll(self.h)
+
+    def field(self, slot: int, name: str) -> np.ndarray:
+        w = self.meta[slot]
+        return ek_batch_get_fields(self.h, slot, name, w.cells, len(w.species))
+
+    def collect(self, slot: int):
+        w = self.meta.pop(slot)
+        return ek_batch_collect(self.h, slot, len(w.spheres))
+
+    def active(self):
+        return ek_batch_active(self.h)
+
+    def close(self):
+        if self.h is not None:
+            ek_batch_destroy(self.h)
+            self.h = None
+        self._arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # -- convenience wrapper -------------------------------------------------------
