@@ -16,7 +16,11 @@ One JSON line is printed with the contract fields plus:
                    library's stream, against the 8 TB/s HBM peak;
   cpu_baseline  -- the FP64 CPU oracle timed on one step of the same workload;
   kernels       -- per-stage mean times and algorithmic-byte bandwidths;
-  fp64_plain    -- the same workload in FP64.
+  fp64_plain    -- the same workload in FP64;
+  serve         -- the serving loop: 200 seeded requests (box edge 32-128,
+                   1-16 spheres, 1000 steps each) arriving as a Poisson stream
+                   at 0.8 x the capacity measured on a saturated batch of 40;
+                   p50/p99 latency and aggregate MLUPS.
 """
 from __future__ import annotations
 
@@ -133,6 +137,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run the plain copy kernel on buffers of this size (counter calibration)")
     args = ap.parse_args()
@@ -178,6 +184,9 @@ def main():
                              "steps": steps64, "stage_ms": st64,
                              "lb_GBps": b64 / (st64["lb"] * 1e-3) / 1e9}
         out["fp32_over_fp64"] = mlups / m64
+    if not args.no_serve:
+        from paper_1607_04572_amd import serve
+        out["serve"] = serve.serve_benchmark(n_requests=args.serve_requests)
     if args.copy_probe_mib:
         out["copy_probe"] = copy_probe(args.copy_probe_mib)
     if not args.no_cpu_baseline:

@@ -175,7 +175,9 @@ class OracleSim:
     LB stream/collide with the momentum-exchange force taken from the
     populations being streamed; electrostatic force; particle update).
     Reading: the paper does not state the order of these parts within a step;
-    the EK advection uses the fluid velocity of the previous LB step."""
+    the EK advection uses the fluid velocity of the previous LB step.
+    Parity unpinned: no closed form fixes this order (the momentum budget pins
+    how the parts combine, not their order)."""
 
     def __init__(self, params: OrParams, particles: list, rho_init: np.ndarray,
                  static_mask: np.ndarray | None = None,

@@ -236,3 +236,58 @@ def test_fixed_uncharged_sphere_in_fluid_at_rest_stays_at_rest():
     fl = np.tile(s.flag == 0, 19)
     assert np.max(np.abs(s.f[fl] - f0[fl])) < 1e-16
     assert np.max(np.abs(s.last["F_hyd"])) < 1e-14
+
+
+def test_electrostatic_torque_is_dipole_cross_field():
+    """With lambda_B = 0 (no self-field) the electrostatic torque on a charged
+    sphere is kT sum_r rho_b(r) (r - r_p) x E: computed here independently from
+    the particle's charge density and minimum-image arms."""
+    n = 16
+    E = np.array([0.013, -0.004, 0.007])
+    x = np.array([7.3, 8.6, 8.1])
+    s = sim(n, [dict(x=tuple(x), R=3.4, Z=25, M=100, mode=2)], species=((0.3, 1, 0.0),), E=tuple(E), lb=0.0)
+    s.step()
+    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    arm = np.stack([g.reshape(-1) + 0.5 - c for g, c in zip((xx, yy, zz), x)])
+    arm = np.where(arm > n / 2, arm - n, np.where(arm < -n / 2, arm + n, arm))
+    dip = (s.rhob[None, :] * arm).sum(axis=1)
+    assert np.allclose(s.last["T_el"][0], np.cross(dip, E), rtol=1e-12, atol=1e-15)
+    assert np.allclose(s.last["F_el"][0], s.rhob.sum() * E, rtol=1e-12, atol=0)
+
+
+def test_hydrodynamic_torque_opposes_rotation_and_vanishes_for_symmetric_translation():
+    """A sphere spinning in fluid at rest feels a torque against its spin (and
+    no force); a sphere translating along x with mirror-symmetric geometry
+    feels no torque."""
+    spin = sim(20, [dict(x=(10.0, 10.0, 10.0), R=3.5, Z=0, M=100, w=(0.0, 0.0, 0.004), mode=1)],
+               species=((0.3, 1, 0.0),), E=(0, 0, 0), lb=0.0)
+    for _ in range(30):
+        spin.step()
+    T = spin.last["T_hyd"][0]
+    assert T[2] < 0 and abs(T[0]) < 1e-10 * abs(T[2]) and abs(T[1]) < 1e-10 * abs(T[2])
+    assert np.max(np.abs(spin.last["F_hyd"][0])) < 1e-10 * abs(T[2])
+    move = sim(20, [dict(x=(10.0, 10.0, 10.0), R=3.5, Z=0, M=100, v=(0.02, 0.0, 0.0), mode=1)],
+               species=((0.3, 1, 0.0),), E=(0, 0, 0), lb=0.0)
+    for _ in range(10):
+        move.step()
+    F = move.last["F_hyd"][0] + move.last["F_cov"][0]
+    T = move.last["T_hyd"][0] + move.last["T_cov"][0]
+    assert np.max(np.abs(T)) < 1e-12 * abs(F[0])
+
+
+@pytest.mark.parametrize("pv", [True, False])
+def test_initial_state_rule(pv):
+    """Fluid at rest with f_i = w_i; no solute in boundary cells; with partial
+    volumes a fluid cell holds (1 - Psi) of the given concentration."""
+    n = 12
+    p = O.make_params(n, n, n, 1 / 6, 1.0, 0.7, (0, 0, 0), [(0.3, 1), (0.2, -1)], partial_volume=pv)
+    rng = np.random.default_rng(2)
+    rho0 = rng.uniform(0.005, 0.015, 2 * n ** 3)
+    s = O.OracleSim(p, [dict(x=(6.2, 5.9, 6.4), R=3.1, Z=5, M=10)], rho0)
+    assert np.array_equal(s.f.reshape(19, -1), np.tile(W19[:, None], (1, n ** 3)))
+    r = s.rho.reshape(2, -1)
+    r0 = rho0.reshape(2, -1)
+    fl = s.flag == 1
+    assert np.all(r[:, fl] == 0.0)
+    expect = r0[:, ~fl] * ((1.0 - s.psi[~fl]) if pv else 1.0)
+    assert np.array_equal(r[:, ~fl], expect)
