@@ -51,7 +51,7 @@ Layout make_layout(const ek_params* p, size_t ts) {
     };
     L.f = take(2 * 19 * N * ts);
     L.rho = take(2 * (size_t)p->n_species * N * ts);
-    L.u = take(3 * N * ts);
+    L.u = take(2 * 3 * N * ts);
     L.fext = take(3 * N * ts);
     L.phi = take(N * ts);
     L.rhob = take(N * ts);
@@ -178,7 +178,8 @@ void setup_sim(ek_ctx* c, Sim<T>& s) {
     s.f[1] = s.f[0] + 19 * N;
     s.rho[0] = (T*)(A + L.rho);
     s.rho[1] = s.rho[0] + (long)p->n_species * N;
-    s.u = (T*)(A + L.u);
+    s.u[0] = (T*)(A + L.u);
+    s.u[1] = s.u[0] + 3 * N;
     s.fext = (T*)(A + L.fext);
     s.phi = (T*)(A + L.phi);
     s.rhob = (T*)(A + L.rhob);
@@ -217,7 +218,7 @@ int init_fields(ek_ctx* c, Sim<T>& s) {
         for (int k = 0; k < p->n_species; ++k)
             fill<T>(s.rho[b] + (long)k * N, N,
                     dev ? (T)0 : (T)(p->species[k].mean_density * p->agrid * p->agrid * p->agrid), st);
-    fill<T>(s.u, 3 * N, (T)0, st);
+    fill<T>(s.u[0], 2 * 3 * N, (T)0, st);
     fill<T>(s.fext, 3 * N, (T)0, st);
     fill<T>(s.phi, N, (T)0, st);
     fill<T>(s.rhob, N, (T)0, st);
@@ -251,9 +252,8 @@ void enqueue_step(const ek_ctx* c, Sim<T> s) {
     launch_boundary(s, st);
     if (!s.pv) launch_refill(s, st);
     launch_charge_poisson(s, st);
-    launch_ek(s, st);
     launch_hydro(s, st);
-    launch_lb(s, st);
+    launch_fields(s, st);
     launch_forces(s, st);
     launch_finish(s, st);
 }
@@ -272,11 +272,9 @@ void enqueue_step_timed(const ek_ctx* c, Sim<T> s, hipEvent_t* ev) {
     (void)hipEventRecord(ev[3], st);
     launch_charge_poisson(s, st);
     (void)hipEventRecord(ev[4], st);
-    launch_ek(s, st);
-    (void)hipEventRecord(ev[5], st);
     launch_hydro(s, st);
-    (void)hipEventRecord(ev[6], st);
-    launch_lb(s, st);
+    (void)hipEventRecord(ev[5], st);
+    launch_fields(s, st, ev[6]);
     (void)hipEventRecord(ev[7], st);
     launch_forces(s, st);
     (void)hipEventRecord(ev[8], st);
@@ -455,7 +453,7 @@ int get_field(ek_ctx* c, Sim<T>& s, int field, void* host, size_t bytes) {
     switch (field) {
         case EK_FIELD_DENSITY: src = s.rho[cur]; break;
         case EK_FIELD_PHI: src = s.phi; break;
-        case EK_FIELD_VELOCITY: src = s.u; break;
+        case EK_FIELD_VELOCITY: src = s.u[cur]; break;
         case EK_FIELD_FORCE: src = s.fext; break;
         case EK_FIELD_POPULATIONS:
         case EK_FIELD_FLUID_DENSITY: src = s.f[cur]; break;
@@ -507,7 +505,7 @@ int set_field(ek_ctx* c, Sim<T>& s, int field, const void* host, size_t bytes) {
                 for (long i = 0; i < N; ++i) h[q * N + i] = (T)(in[q * N + i] / fac - (dev ? q19w(q) : 0.0));
             break;
         case EK_FIELD_PHI: dst = s.phi; break;
-        case EK_FIELD_VELOCITY: dst = s.u; break;
+        case EK_FIELD_VELOCITY: dst = s.u[cur]; break;
         case EK_FIELD_FORCE: dst = s.fext; break;
         default: return EK_ERR_INVALID_ARG;
     }
@@ -741,7 +739,7 @@ int ek_profile_stages(ek_ctx* c, int n, double* ms_out, int n_out) {
 }
 
 int ek_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
-    if (!dst || !src || bytes % 16) return EK_ERR_INVALID_ARG;
+    if (!dst || !src || bytes % 16 || bytes > ((size_t)1 << 40)) return EK_ERR_INVALID_ARG;
     launch_copy16(dst, src, (long)(bytes / 16), (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? EK_OK : EK_ERR_DEVICE;
 }
@@ -999,9 +997,8 @@ int push_table(ek_batch* b) {
 void enqueue_batch_step(ek_batch* b) {
     launch_batch_particles_pre(b->dtab, b->stream);
     launch_batch_poisson(b->dtab, b->stream);
-    launch_batch_ek(b->dtab, b->ns, b->stream);
     launch_batch_hydro(b->dtab, b->stream);
-    launch_batch_lb(b->dtab, b->stream);
+    launch_batch_fields(b->dtab, b->ns, b->stream);
     launch_batch_particles_post(b->dtab, b->stream);
     launch_batch_flip(b->dtab, b->stream);
 }

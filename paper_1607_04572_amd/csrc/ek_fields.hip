@@ -1,4 +1,4 @@
-// ek_fields.hip -- the two full-lattice stencil kernels of a step.
+// ek_fields.hip -- the full-lattice stencil kernels of a step.
 //
 // k_ek: Nernst-Planck solute update (Sec. III.C, III.D.2).  For each cell, the
 //   flux on each of its 26 links is evaluated (13 directions, both ends), the
@@ -23,6 +23,11 @@
 //   f_i* = f_i + le (f_i+ - feq_i+) + lo (f_i- - feq_i-) + Delta_i,
 //   feq_i+ = w_i (rho + 9/2 (c.u)^2 - 3/2 u^2),  feq_i- = 3 w_i c.j,
 //   Delta_i = 3 w_i [c.f + 3/2 (2+le)((c.u)(c.f) - u.f/3)].
+// k_ek<..., FUSE>: both in one pass (used for FP64): each thread finishes its
+//   cell's EK update and then streams/collides the same cell with the coupling
+//   force still in registers.  The velocity is double-buffered (EK reads
+//   u[cur], LB writes u[cur^1]) so that the two can interleave across
+//   workgroups.
 // On the FP32 path populations are stored as f_i - w_i and densities as
 // rho_k - mean_k; every formula above is linear in those offsets except the
 // explicit mean terms, which are carried exactly.
@@ -35,6 +40,124 @@ constexpr int BT = 256;
 template <typename T>
 __device__ __forceinline__ long cidx3(const Sim<T>& s, int x, int y, int z) {
     return (long)x + (long)s.nx * ((long)y + (long)s.ny * z);
+}
+
+// ---------------------------------------------------------------------------
+// LB cell update (used by the fused EK+LB kernel and the unfused LB kernel)
+// ---------------------------------------------------------------------------
+// Periodic neighbour coordinates of one cell.
+struct Nbr {
+    int x, y, z, xm, xp, ym, yp, zm, zp;
+    __device__ __forceinline__ Nbr(int x_, int y_, int z_, int nx, int ny, int nz) : x(x_), y(y_), z(z_) {
+        xm = x == 0 ? nx - 1 : x - 1;
+        xp = x == nx - 1 ? 0 : x + 1;
+        ym = y == 0 ? ny - 1 : y - 1;
+        yp = y == ny - 1 ? 0 : y + 1;
+        zm = z == 0 ? nz - 1 : z - 1;
+        zp = z == nz - 1 ? 0 : z + 1;
+    }
+    // source cell r - c_i of population i
+    template <typename T>
+    __device__ __forceinline__ long src(const Sim<T>& s, int i) const {
+        const int sx = q19x(i) > 0 ? xm : (q19x(i) < 0 ? xp : x);
+        const int sy = q19y(i) > 0 ? ym : (q19y(i) < 0 ? yp : y);
+        const int sz = q19z(i) > 0 ? zm : (q19z(i) < 0 ? zp : z);
+        return cidx3(s, sx, sy, sz);
+    }
+};
+
+// Pull every population from its source r - c_i (independent loads).
+template <typename T>
+__device__ __forceinline__ void lb_pull(const Sim<T>& s, const Nbr& nb, T (&fi)[19]) {
+    const T* __restrict__ fs = s.f[s.cur];
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        fi[i] = fs[(long)i * s.N + nb.src<T>(s, i)];
+    });
+}
+
+// Boundary-cell sources (bit i of bmask: r - c_i is a boundary cell).
+template <typename T>
+__device__ __forceinline__ unsigned lb_bmask_global(const Sim<T>& s, const Nbr& nb) {
+    unsigned bmask = 0;
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i > 0) bmask |= (unsigned)(s.flag[nb.src<T>(s, i)] & F_CUR) << i;
+    });
+    return bmask;
+}
+
+// Stream/collide of fluid cell c with pulled populations fi, force density
+// (fx, fy, fz) and boundary-source mask bmask; writes f* and u.
+template <typename T, bool DEV>
+__device__ __forceinline__ void lb_collide(const Sim<T>& s, long c, const Nbr& nb, T (&fi)[19], unsigned bmask, T fx,
+                                           T fy, T fz) {
+    const T* __restrict__ fs = s.f[s.cur];
+    T* __restrict__ fd = s.f[s.cur ^ 1];
+    T* __restrict__ uo = s.u[s.cur ^ 1];
+    if (bmask) {
+        const int nx = s.nx, ny = s.ny, nz = s.nz;
+        sfor<19>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) {
+                if (bmask & (1u << i)) {
+                    // moving bounce-back from the boundary cell b = r - c_i
+                    const long b = nb.src<T>(s, i);
+                    double vb[3] = {0.0, 0.0, 0.0};
+                    uint16_t ow = s.owner[b];
+                    if (ow != NO_OWNER) {
+                        const PState& q = s.parts[ow];
+                        const int bx = (int)(b % nx), by = (int)((b / nx) % ny), bz = (int)(b / ((long)nx * ny));
+                        double r[3] = {min_image((double)bx + 0.5, q.x[0], (double)nx),
+                                       min_image((double)by + 0.5, q.x[1], (double)ny),
+                                       min_image((double)bz + 0.5, q.x[2], (double)nz)};
+                        vb[0] = q.v[0] + (q.w[1] * r[2] - q.w[2] * r[1]);
+                        vb[1] = q.v[1] + (q.w[2] * r[0] - q.w[0] * r[2]);
+                        vb[2] = q.v[2] + (q.w[0] * r[1] - q.w[1] * r[0]);
+                    }
+                    double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
+                    fi[i] = fs[(long)q19opp(i) * s.N + c] + (T)(6.0 * q19w(i) * cv);
+                }
+            }
+        });
+    }
+    T rho = (T)0, jx = (T)0, jy = (T)0, jz = (T)0;
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        rho += fi[i];
+        if constexpr (q19x(i) != 0) jx += (T)q19x(i) * fi[i];
+        if constexpr (q19y(i) != 0) jy += (T)q19y(i) * fi[i];
+        if constexpr (q19z(i) != 0) jz += (T)q19z(i) * fi[i];
+    });
+    const T ux = jx + (T)0.5 * fx, uy = jy + (T)0.5 * fy, uz = jz + (T)0.5 * fz;
+    const T usq = ux * ux + uy * uy + uz * uz;
+    const T uf = ux * fx + uy * fy + uz * fz;
+    const T le = s.lam_e, lo = s.lam_o;
+    const T g2 = (T)2 + le;
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        constexpr int o = q19opp(i);
+        const T w = (T)q19w(i);
+        const T cu = (T)q19x(i) * ux + (T)q19y(i) * uy + (T)q19z(i) * uz;
+        const T cj = (T)q19x(i) * jx + (T)q19y(i) * jy + (T)q19z(i) * jz;
+        const T cf = (T)q19x(i) * fx + (T)q19y(i) * fy + (T)q19z(i) * fz;
+        const T feq_e = w * (rho + (T)4.5 * cu * cu - (T)1.5 * usq);
+        const T feq_o = w * (T)3 * cj;
+        const T fp = (T)0.5 * (fi[i] + fi[o]);
+        const T fm = (T)0.5 * (fi[i] - fi[o]);
+        const T delta = (T)3 * w * (cf + (T)1.5 * (g2 * cu * cf - g2 * uf / (T)3));
+        __builtin_nontemporal_store(fi[i] + le * (fp - feq_e) + lo * (fm - feq_o) + delta, &fd[(long)i * s.N + c]);
+    });
+    __builtin_nontemporal_store(ux, &uo[c]);
+    __builtin_nontemporal_store(uy, &uo[s.N + c]);
+    __builtin_nontemporal_store(uz, &uo[2 * s.N + c]);
+}
+
+// Velocity of a boundary cell (no populations are streamed there).
+template <typename T>
+__device__ __forceinline__ void lb_wall(const Sim<T>& s, long c) {
+    T* __restrict__ uo = s.u[s.cur ^ 1];
+    uo[c] = uo[s.N + c] = uo[2 * s.N + c] = (T)0;
 }
 
 // ---------------------------------------------------------------------------
@@ -162,9 +285,9 @@ __device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, T
         uint8_t fl = s.flag[c];
         r.v[NS] = s.phi[c];
         r.v[NS + 1] = (T)psi;
-        r.v[NS + 2] = s.u[c];
-        r.v[NS + 3] = s.u[s.N + c];
-        r.v[NS + 4] = s.u[2 * s.N + c];
+        r.v[NS + 2] = s.u[s.cur][c];
+        r.v[NS + 3] = s.u[s.cur][s.N + c];
+        r.v[NS + 4] = s.u[s.cur][2 * s.N + c];
         r.v[NS + 5] = (fl & F_CUR) ? (T)1 : (T)0;
 #pragma unroll
         for (int k = NS + 6; k < RecEK<T, NS>::NV; ++k) r.v[k] = (T)0;
@@ -215,9 +338,34 @@ __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T
     });
 }
 
+// Boundary-cell sources of one cell's populations from the staged flags.
+template <typename T, int NS, int TXW, int TYW>
+__device__ __forceinline__ unsigned lb_bmask_lds(const EKShared<T, NS, TXW, TYW>& sh, int ctr, int s0, int sm,
+                                                 int sp) {
+    using SH = EKShared<T, NS, TXW, TYW>;
+    unsigned m = 0;
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i > 0) {
+            constexpr int cx = q19x(i), cy = q19y(i), cz = q19z(i);
+            const int slot = cz > 0 ? sm : (cz < 0 ? sp : s0);
+            m |= (unsigned)sh.rec[slot][ctr - cy * SH::WX - cx].wall() << i;
+        }
+    });
+    return m;
+}
+
 // Grid: tiles of TXW x TYW cells in x-y times z-chunks of ZC planes, flattened
 // and mapped with xcd_tile; each workgroup marches its ZC planes.
-template <typename T, bool DEV, int NS, int TXW, int TYW>
+// FUSE: the cell's LB stream/collide follows its EK update in the same thread,
+// with the coupling force taken from registers (the force field is still
+// written for readers of the state).  The velocity the EK advection reads
+// (u[cur]) and the one LB writes (u[cur^1]) are different buffers, so the
+// order of cells across workgroups does not matter.  The populations of a
+// cell are requested at the start of its z-iteration, before the next plane
+// is staged, so that their latency overlaps the staging and the flux work
+// (PREFETCH), or after the flux work (fewer registers live across it).
+template <typename T, bool DEV, int NS, int TXW, int TYW, bool FUSE, bool PREFETCH = true>
 __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int gx_, int ZC, int gx, int gy, int ntiles) {
     using SH = EKShared<T, NS, TXW, TYW>;
     __shared__ SH sh;
@@ -252,18 +400,23 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
     const int tx = threadIdx.x % TXW, ty = threadIdx.x / TXW;
     const int x = x0 + tx, y = y0 + ty;
     const bool valid = x < s.nx && y < s.ny;
+    const int ctr = (ty + 1) * SH::WX + (tx + 1);
     const int zend = zbeg + ZC < s.nz ? zbeg + ZC : s.nz;
     for (int z = zbeg; z < zend; ++z) {
-        bool dn = ek_load_plane<T, NS, TXW, TYW>(s, sh, (z + 1) % 3, x0, y0, z + 1, rin);
-        int an = __syncthreads_or(dn);
-        if (threadIdx.x == 0) sh.dirty[(z + 1) % 3] = an;
-        __syncthreads();
         const int sm = (z + 2) % 3, s0 = z % 3, sp = (z + 1) % 3;
+        // plane z is staged since the previous iteration
+        const bool wall = valid && sh.rec[s0][ctr].wall();
+        T fi[FUSE ? 19 : 1];
+        if constexpr (FUSE && PREFETCH) {
+            if (valid && !wall) lb_pull(s, Nbr(x, y, z, s.nx, s.ny, s.nz), fi);
+        }
+        bool dn = ek_load_plane<T, NS, TXW, TYW>(s, sh, sp, x0, y0, z + 1, rin);
+        int an = __syncthreads_or(dn);
+        if (threadIdx.x == 0) sh.dirty[sp] = an;
+        __syncthreads();
         const bool clean = !(sh.dirty[0] | sh.dirty[1] | sh.dirty[2]);
         if (valid) {
-            const int ctr = (ty + 1) * SH::WX + (tx + 1);
             long c = cidx3(s, x, y, z);
-            const bool wall = sh.rec[s0][ctr].wall();
             T dr[NS];
             T fe[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
@@ -285,110 +438,44 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
             __builtin_nontemporal_store(fe[0], &s.fext[c]);
             __builtin_nontemporal_store(fe[1], &s.fext[s.N + c]);
             __builtin_nontemporal_store(fe[2], &s.fext[2 * s.N + c]);
+            if constexpr (FUSE) {
+                if (wall) {
+                    lb_wall(s, c);
+                } else {
+                    const Nbr nb(x, y, z, s.nx, s.ny, s.nz);
+                    if constexpr (!PREFETCH) lb_pull(s, nb, fi);
+                    const unsigned bmask = clean ? 0u : lb_bmask_lds<T, NS, TXW, TYW>(sh, ctr, s0, sm, sp);
+                    lb_collide<T, DEV>(s, c, nb, fi, bmask, fe[0], fe[1], fe[2]);
+                }
+            }
         }
         __syncthreads();
     }
 }
 
-template <typename T, bool DEV, int NS, int TXW, int TYW>
+template <typename T, bool DEV, int NS, int TXW, int TYW, bool FUSE, bool PREFETCH>
 __global__ __launch_bounds__(TXW* TYW) void k_ek(Sim<T> s, int ZC, int gx, int gy, int ntiles) {
-    ek_body<T, DEV, NS, TXW, TYW>(s, blockIdx.x, blockIdx.y, gridDim.x, ZC, gx, gy, ntiles);
+    ek_body<T, DEV, NS, TXW, TYW, FUSE, PREFETCH>(s, blockIdx.x, blockIdx.y, gridDim.x, ZC, gx, gy, ntiles);
 }
 
 // ---------------------------------------------------------------------------
-// LB
+// LB (unfused kernel)
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
 __device__ __forceinline__ void lb_body(const Sim<T>& s, int bx_, int by_, int gx_) {
     long c = (long)bx_ * BT + threadIdx.x;
     if (c >= s.N) return;
-    const int nx = s.nx, ny = s.ny, nz = s.nz;
-    int x = (int)(c % nx);
-    int y = (int)((c / nx) % ny);
-    int z = (int)(c / ((long)nx * ny));
-    const uint8_t fl = s.flag[c];
-    if (fl & F_CUR) {
-        s.u[c] = s.u[s.N + c] = s.u[2 * s.N + c] = (T)0;
+    const int nx = s.nx, ny = s.ny;
+    const Nbr nb((int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long)nx * ny)), nx, ny, s.nz);
+    if (s.flag[c] & F_CUR) {
+        lb_wall(s, c);
         return;
     }
-    const T* __restrict__ fs = s.f[s.cur];
-    T* __restrict__ fd = s.f[s.cur ^ 1];
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-    // Pull every population from its source r - c_i first (independent loads),
-    // then replace those whose source is a boundary cell (rare).
+    // all loads first, boundary fix-ups (rare) afterwards
     T fi[19];
-    long src[19];
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        const int sx = q19x(i) > 0 ? xm : (q19x(i) < 0 ? xp : x);
-        const int sy = q19y(i) > 0 ? ym : (q19y(i) < 0 ? yp : y);
-        const int sz = q19z(i) > 0 ? zm : (q19z(i) < 0 ? zp : z);
-        src[i] = cidx3(s, sx, sy, sz);
-        fi[i] = fs[(long)i * s.N + src[i]];
-    });
+    lb_pull(s, nb, fi);
     const T fx = s.fext[c], fy = s.fext[s.N + c], fz = s.fext[2 * s.N + c];
-    unsigned bmask = 0;
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        if constexpr (i > 0) bmask |= (unsigned)(s.flag[src[i]] & F_CUR) << i;
-    });
-    if (bmask) {
-        sfor<19>([&](auto I) {
-            constexpr int i = I;
-            if constexpr (i > 0) {
-                if (bmask & (1u << i)) {
-                    // moving bounce-back from the boundary cell src
-                    const long b = src[i];
-                    double vb[3] = {0.0, 0.0, 0.0};
-                    uint16_t ow = s.owner[b];
-                    if (ow != NO_OWNER) {
-                        const PState& q = s.parts[ow];
-                        const int bx = (int)(b % nx), by = (int)((b / nx) % ny), bz = (int)(b / ((long)nx * ny));
-                        double r[3] = {min_image((double)bx + 0.5, q.x[0], (double)nx),
-                                       min_image((double)by + 0.5, q.x[1], (double)ny),
-                                       min_image((double)bz + 0.5, q.x[2], (double)nz)};
-                        vb[0] = q.v[0] + (q.w[1] * r[2] - q.w[2] * r[1]);
-                        vb[1] = q.v[1] + (q.w[2] * r[0] - q.w[0] * r[2]);
-                        vb[2] = q.v[2] + (q.w[0] * r[1] - q.w[1] * r[0]);
-                    }
-                    double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
-                    fi[i] = fs[(long)q19opp(i) * s.N + c] + (T)(6.0 * q19w(i) * cv);
-                }
-            }
-        });
-    }
-    T rho = (T)0, jx = (T)0, jy = (T)0, jz = (T)0;
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        rho += fi[i];
-        if constexpr (q19x(i) != 0) jx += (T)q19x(i) * fi[i];
-        if constexpr (q19y(i) != 0) jy += (T)q19y(i) * fi[i];
-        if constexpr (q19z(i) != 0) jz += (T)q19z(i) * fi[i];
-    });
-    const T ux = jx + (T)0.5 * fx, uy = jy + (T)0.5 * fy, uz = jz + (T)0.5 * fz;
-    const T usq = ux * ux + uy * uy + uz * uz;
-    const T uf = ux * fx + uy * fy + uz * fz;
-    const T le = s.lam_e, lo = s.lam_o;
-    const T g2 = (T)2 + le;
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        constexpr int o = q19opp(i);
-        const T w = (T)q19w(i);
-        const T cu = (T)q19x(i) * ux + (T)q19y(i) * uy + (T)q19z(i) * uz;
-        const T cj = (T)q19x(i) * jx + (T)q19y(i) * jy + (T)q19z(i) * jz;
-        const T cf = (T)q19x(i) * fx + (T)q19y(i) * fy + (T)q19z(i) * fz;
-        const T feq_e = w * (rho + (T)4.5 * cu * cu - (T)1.5 * usq);
-        const T feq_o = w * (T)3 * cj;
-        const T fp = (T)0.5 * (fi[i] + fi[o]);
-        const T fm = (T)0.5 * (fi[i] - fi[o]);
-        const T delta = (T)3 * w * (cf + (T)1.5 * (g2 * cu * cf - g2 * uf / (T)3));
-        __builtin_nontemporal_store(fi[i] + le * (fp - feq_e) + lo * (fm - feq_o) + delta, &fd[(long)i * s.N + c]);
-    });
-    __builtin_nontemporal_store(ux, &s.u[c]);
-    __builtin_nontemporal_store(uy, &s.u[s.N + c]);
-    __builtin_nontemporal_store(uz, &s.u[2 * s.N + c]);
+    lb_collide<T, DEV>(s, c, nb, fi, lb_bmask_global(s, nb), fx, fy, fz);
 }
 
 template <typename T, bool DEV>
@@ -397,34 +484,46 @@ __global__ __launch_bounds__(BT) void k_lb(Sim<T> s) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, bool DEV, int NS>
+// Launchers.  FP64 runs the fused EK+LB kernel (populations pulled after the
+// flux work): the flux work is ALU-bound and the stream/collide HBM-bound, and
+// at FP64 register counts the interleaving pays (about 15 % over two
+// kernels).  In FP32 two kernels are faster: the stand-alone LB kernel streams
+// whole 1 KB rows per population at higher occupancy than the tiled fused pass.
+// ---------------------------------------------------------------------------
+template <typename T> constexpr bool kFuseFields = sizeof(T) == 8;
+template <typename T> constexpr bool kPrefetch = false;
+
+template <typename T, bool DEV, int NS, bool FUSE>
 static void launch_ek_ns(const Sim<T>& s, hipStream_t st) {
     constexpr int TXW = EKTile<T>::TXW, TYW = EKTile<T>::TYW;
     Grids<T> g = grids_of<T>(s);
     int nt = g.n[KK_EK];
-    hipLaunchKernelGGL((k_ek<T, DEV, NS, TXW, TYW>), dim3(nt), dim3(TXW * TYW), 0, st, s, EKTile<T>::ZC, g.ek_gx,
-                       g.ek_gy, nt);
+    hipLaunchKernelGGL((k_ek<T, DEV, NS, TXW, TYW, FUSE, kPrefetch<T>>), dim3(nt), dim3(TXW * TYW), 0, st, s,
+                       EKTile<T>::ZC, g.ek_gx, g.ek_gy, nt);
 }
 
-template <typename T>
-void launch_ek(const Sim<T>& s, hipStream_t st) {
+template <typename T, bool FUSE>
+static void launch_ek(const Sim<T>& s, hipStream_t st) {
     constexpr bool DEV = sizeof(T) == 4;
     switch (s.ns) {
-        case 1: launch_ek_ns<T, DEV, 1>(s, st); break;
-        case 2: launch_ek_ns<T, DEV, 2>(s, st); break;
-        case 3: launch_ek_ns<T, DEV, 3>(s, st); break;
-        default: launch_ek_ns<T, DEV, 4>(s, st); break;
+        case 1: launch_ek_ns<T, DEV, 1, FUSE>(s, st); break;
+        case 2: launch_ek_ns<T, DEV, 2, FUSE>(s, st); break;
+        case 3: launch_ek_ns<T, DEV, 3, FUSE>(s, st); break;
+        default: launch_ek_ns<T, DEV, 4, FUSE>(s, st); break;
     }
 }
 
 template <typename T>
-void launch_lb(const Sim<T>& s, hipStream_t st) {
+void launch_fields(const Sim<T>& s, hipStream_t st, hipEvent_t mid) {
     constexpr bool DEV = sizeof(T) == 4;
-    hipLaunchKernelGGL((k_lb<T, DEV>), dim3((unsigned)((s.N + BT - 1) / BT)), dim3(BT), 0, st, s);
+    launch_ek<T, kFuseFields<T>>(s, st);
+    if (mid) (void)hipEventRecord(mid, st);
+    if constexpr (!kFuseFields<T>)
+        hipLaunchKernelGGL((k_lb<T, DEV>), dim3((unsigned)((s.N + BT - 1) / BT)), dim3(BT), 0, st, s);
 }
 
 // ---------------------------------------------------------------------------
-// Batched EK and LB (FP32 tables)
+// Batched EK and LB (FP32 tables), same split as the single-simulation path.
 // ---------------------------------------------------------------------------
 constexpr int BATCH_FIELD_BLOCKS = 2048;
 
@@ -434,7 +533,7 @@ __global__ __launch_bounds__(EKTile<float>::TXW* EKTile<float>::TYW) void kb_ek(
     batch_loop<KK_EK>(tab, [](const Sim<float>& s, int b) {
         const int gx = (s.nx + TXW - 1) / TXW, gy = (s.ny + TYW - 1) / TYW;
         const int nt = gx * gy * ((s.nz + ZC - 1) / ZC);
-        ek_body<float, true, NS, TXW, TYW>(s, b, 0, 0, ZC, gx, gy, nt);
+        ek_body<float, true, NS, TXW, TYW, kFuseFields<float>, kPrefetch<float>>(s, b, 0, 0, ZC, gx, gy, nt);
     });
 }
 
@@ -442,7 +541,7 @@ __global__ __launch_bounds__(BT) void kb_lb(const BatchTable* tab) {
     batch_loop<KK_LB>(tab, [](const Sim<float>& s, int b) { lb_body<float, true>(s, b, 0, 0); });
 }
 
-void launch_batch_ek(const BatchTable* tab, int ns, hipStream_t st) {
+void launch_batch_fields(const BatchTable* tab, int ns, hipStream_t st) {
     constexpr int NT = EKTile<float>::TXW * EKTile<float>::TYW;
     switch (ns) {
         case 1: hipLaunchKernelGGL(kb_ek<1>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
@@ -450,15 +549,10 @@ void launch_batch_ek(const BatchTable* tab, int ns, hipStream_t st) {
         case 3: hipLaunchKernelGGL(kb_ek<3>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
         default: hipLaunchKernelGGL(kb_ek<4>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
     }
+    if constexpr (!kFuseFields<float>) hipLaunchKernelGGL(kb_lb, dim3(BATCH_FIELD_BLOCKS), dim3(BT), 0, st, tab);
 }
 
-void launch_batch_lb(const BatchTable* tab, hipStream_t st) {
-    hipLaunchKernelGGL(kb_lb, dim3(BATCH_FIELD_BLOCKS), dim3(BT), 0, st, tab);
-}
-
-template void launch_ek<float>(const Sim<float>&, hipStream_t);
-template void launch_ek<double>(const Sim<double>&, hipStream_t);
-template void launch_lb<float>(const Sim<float>&, hipStream_t);
-template void launch_lb<double>(const Sim<double>&, hipStream_t);
+template void launch_fields<float>(const Sim<float>&, hipStream_t, hipEvent_t);
+template void launch_fields<double>(const Sim<double>&, hipStream_t, hipEvent_t);
 
 }  // namespace ek

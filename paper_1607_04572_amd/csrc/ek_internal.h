@@ -107,7 +107,7 @@ struct Sim {
     long n_wall;              // number of wall cells
     T* f[2];
     T* rho[2];
-    T* u;
+    T* u[2];                  // velocity read by EK this step (u[cur]) / written by LB (u[cur^1])
     T* fext;
     T* phi;
     T* rhob;
@@ -130,8 +130,8 @@ struct Sim {
 // ---------------------------------------------------------------------------
 // Launch geometry shared by the single-simulation and batched launches
 // ---------------------------------------------------------------------------
-constexpr int FFT_THREADS = 256;
-constexpr int FFT_ELEMS = 16;   // pencil elements per thread of an FFT workgroup
+constexpr int FFT_THREADS = 512;
+constexpr int FFT_ELEMS = 8;    // pencil elements per thread of an FFT workgroup
 constexpr int POOL_BLOCKS = 64;
 
 // Pencils per workgroup in the x passes (P * n <= 2048).
@@ -234,8 +234,9 @@ template <typename T> void launch_geometry(const Sim<T>& s, hipStream_t st, int 
 template <typename T> void launch_boundary(const Sim<T>& s, hipStream_t st);
 template <typename T> void launch_init_density(const Sim<T>& s, hipStream_t st);
 template <typename T> void launch_charge_poisson(const Sim<T>& s, hipStream_t st);
-template <typename T> void launch_ek(const Sim<T>& s, hipStream_t st);
-template <typename T> void launch_lb(const Sim<T>& s, hipStream_t st);
+// EK + LB update; `mid` (optional) is recorded between the EK and LB kernels,
+// or after the fused kernel where they are one.
+template <typename T> void launch_fields(const Sim<T>& s, hipStream_t st, hipEvent_t mid = nullptr);
 template <typename T> void launch_refill(const Sim<T>& s, hipStream_t st);
 template <typename T> void launch_hydro(const Sim<T>& s, hipStream_t st);
 template <typename T> void launch_forces(const Sim<T>& s, hipStream_t st);
@@ -245,8 +246,7 @@ template <typename T> void launch_diagnostics(const Sim<T>& s, hipStream_t st, d
 // batched step pieces (FP32 tables)
 void launch_batch_particles_pre(const BatchTable* tab, hipStream_t st);
 void launch_batch_poisson(const BatchTable* tab, hipStream_t st);
-void launch_batch_ek(const BatchTable* tab, int ns, hipStream_t st);
-void launch_batch_lb(const BatchTable* tab, hipStream_t st);
+void launch_batch_fields(const BatchTable* tab, int ns, hipStream_t st);
 void launch_batch_hydro(const BatchTable* tab, hipStream_t st);
 void launch_batch_particles_post(const BatchTable* tab, hipStream_t st);
 void launch_batch_flip(BatchTable* tab, hipStream_t st);

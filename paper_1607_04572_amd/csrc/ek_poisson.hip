@@ -83,6 +83,16 @@ __device__ __forceinline__ void dft_small(cpx<T> (&v)[R]) {
     }
 }
 
+// Division by a workgroup-uniform divisor 1 <= d <= 2^16 for dividends
+// 0 <= x < 2^16: q = floor(x * ceil(2^32 / d) / 2^32) is exact there (the
+// rounding error of the reciprocal, below x / 2^32, never reaches 1/d).
+struct FDiv {
+    uint32_t m;
+    int d;
+    __device__ __forceinline__ explicit FDiv(int d_) : m(d_ == 1 ? 0u : 0xFFFFFFFFu / (uint32_t)d_ + 1u), d(d_) {}
+    __device__ __forceinline__ int div(int x) const { return d == 1 ? x : (int)__umulhi((uint32_t)x, m); }
+};
+
 // One in-place Stockham stage of radix R over P pencils of length n stored at
 // a[p * ld + index].  Every thread first loads all inputs of its butterflies
 // into registers, the workgroup synchronises, then the outputs are written to
@@ -98,6 +108,7 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
     const int nR = n / R;
     const int span = n / (Ns * R);
     const int nb = P * nR;
+    const FDiv dnR(nR), dNs(Ns);
     cpx<T> v[NB][R];
     int dst[NB];
 #pragma unroll
@@ -105,8 +116,8 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
         int b = threadIdx.x + q * FT;
         dst[q] = -1;
         if (b < nb) {
-            int pen = b / nR, j = b - pen * nR;
-            int k = j % Ns;
+            int pen = dnR.div(b), j = b - pen * nR;
+            int jq = dNs.div(j), k = j - jq * Ns;
             const cpx<T>* src = a + pen * ld;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -118,7 +129,7 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
                 }
                 v[q][r] = x;
             }
-            dst[q] = pen * ld + (j / Ns) * Ns * R + k;
+            dst[q] = pen * ld + jq * Ns * R + k;
         }
     }
     __syncthreads();
@@ -169,8 +180,9 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
     const int npairs = s.ny * s.nz / 2;
     const int pair0 = bx_ * P;
     const T* rho = s.rho[s.cur];
+    const FDiv dn(n), dnh(s.nxh);
     for (int t = threadIdx.x; t < P * n; t += FT) {
-        int pen = t / n, x = t - pen * n;
+        int pen = dn.div(t), x = t - pen * n;
         int pr = pair0 + pen;
         cpx<T> v = mk<T>(0, 0);
         if (pr < npairs) {
@@ -192,7 +204,7 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
     const int nh = s.nxh;
     for (int t = threadIdx.x; t < P * nh; t += FT) {
-        int pen = t / nh, k = t - pen * nh;
+        int pen = dnh.div(t), k = t - pen * nh;
         int pr = pair0 + pen;
         if (pr >= npairs) continue;
         cpx<T> A = r[pen * ld + k];
@@ -223,8 +235,9 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
     const int npairs = s.ny * s.nz / 2;
     const int pair0 = bx_ * P;
     const cpx<T>* S = reinterpret_cast<const cpx<T>*>(s.spec);
+    const FDiv dn(n);
     for (int t = threadIdx.x; t < P * n; t += FT) {
-        int pen = t / n, k = t - pen * n;
+        int pen = dn.div(t), k = t - pen * n;
         int pr = pair0 + pen;
         cpx<T> v = mk<T>(0, 0);
         if (pr < npairs) {
@@ -242,7 +255,7 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
     __syncthreads();
     fft_lds<T, true>(a, n, P, ld, reinterpret_cast<const cpx<T>*>(s.tw[0]));
     for (int t = threadIdx.x; t < P * n; t += FT) {
-        int pen = t / n, x = t - pen * n;
+        int pen = dn.div(t), x = t - pen * n;
         int pr = pair0 + pen;
         if (pr >= npairs) continue;
         long c0 = (long)(2 * pr) * n + x;
@@ -269,15 +282,16 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int by_, in
     int z = bx_ / tiles;
     int kx0 = (bx_ - z * tiles) * TX;
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec) + (long)z * n * nh;
+    const FDiv dtx(TX);
     for (int t = threadIdx.x; t < TX * n; t += FT) {
-        int y = t / TX, i = t - y * TX;
+        int y = dtx.div(t), i = t - y * TX;
         int kx = kx0 + i;
         a[i * ld + y] = kx < nh ? S[(long)y * nh + kx] : mk<T>(0, 0);
     }
     __syncthreads();
     fft_lds<T, INV>(a, n, TX, ld, reinterpret_cast<const cpx<T>*>(s.tw[1]));
     for (int t = threadIdx.x; t < TX * n; t += FT) {
-        int y = t / TX, i = t - y * TX;
+        int y = dtx.div(t), i = t - y * TX;
         int kx = kx0 + i;
         if (kx < nh) S[(long)y * nh + kx] = a[i * ld + y];
     }
@@ -301,8 +315,9 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
     int kx0 = (bx_ - ky * tiles) * TX;
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
     const long zstride = (long)ny * nh;
+    const FDiv dtx(TX), dn(n);
     for (int t = threadIdx.x; t < TX * n; t += FT) {
-        int z = t / TX, i = t - z * TX;
+        int z = dtx.div(t), i = t - z * TX;
         int kx = kx0 + i;
         a[i * ld + z] = kx < nh ? S[z * zstride + (long)ky * nh + kx] : mk<T>(0, 0);
     }
@@ -310,7 +325,7 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
     fft_lds<T, false>(a, n, TX, ld, reinterpret_cast<const cpx<T>*>(s.tw[2]));
     const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
     for (int t = threadIdx.x; t < TX * n; t += FT) {
-        int i = t / n, kz = t - i * n;
+        int i = dn.div(t), kz = t - i * n;
         int kx = kx0 + i;
         T g = 0;
         if (kx < nh) {
@@ -323,7 +338,7 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
     __syncthreads();
     fft_lds<T, true>(a, n, TX, ld, reinterpret_cast<const cpx<T>*>(s.tw[2]));
     for (int t = threadIdx.x; t < TX * n; t += FT) {
-        int z = t / TX, i = t - z * TX;
+        int z = dtx.div(t), i = t - z * TX;
         int kx = kx0 + i;
         if (kx < nh) S[z * zstride + (long)ky * nh + kx] = a[i * ld + z];
     }
