@@ -272,11 +272,16 @@ template <typename T, int NS, int TXW, int TYW>
 __device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, TXW, TYW>& sh, int slot, int x0,
                                               int y0, int z, const T* __restrict__ rin) {
     using SH = EKShared<T, NS, TXW, TYW>;
-    int zz = wrapi(z, s.nz);
+    const int zz = wrap1(z, s.nz);  // z in [-1, nz]
     bool dirty = false;
     for (int t = threadIdx.x; t < SH::WPL; t += TXW * TYW) {
         int i = t % SH::WX, j = t / SH::WX;
-        int x = wrapi(x0 + i - 1, s.nx), y = wrapi(y0 + j - 1, s.ny);
+        // Records up to one past the tile's last valid cell wrap periodically;
+        // those beyond (tiles wider than a small domain) serve no valid cell
+        // and are clamped into range.
+        int x = wrap1(x0 + i - 1, s.nx), y = wrap1(y0 + j - 1, s.ny);
+        x = x < s.nx ? x : s.nx - 1;
+        y = y < s.ny ? y : s.ny - 1;
         long c = cidx3(s, x, y, zz);
         RecEK<T, NS> r;
 #pragma unroll

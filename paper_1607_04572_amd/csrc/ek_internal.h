@@ -212,10 +212,19 @@ __device__ __forceinline__ void batch_loop(const BatchTable* tab, F&& f) {
     }
 }
 
-__device__ __forceinline__ int wrapi(int i, int n) {
-    i %= n;
-    return i < 0 ? i + n : i;
-}
+// i mod n for -n <= i < 2n (one conditional correction, no division).
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Division by a workgroup-uniform divisor 1 <= d < 2^16 for dividends
+// 0 <= x with x * d < 2^32: q = floor(x * ceil(2^32 / d) / 2^32) is exact
+// there (the rounding error of the reciprocal, below x / 2^32, never reaches
+// 1/d).
+struct FDiv {
+    uint32_t m;
+    int d;
+    __device__ __forceinline__ explicit FDiv(int d_) : m(d_ == 1 ? 0u : 0xFFFFFFFFu / (uint32_t)d_ + 1u), d(d_) {}
+    __device__ __forceinline__ int div(int x) const { return d == 1 ? x : (int)__umulhi((uint32_t)x, m); }
+};
 
 // Minimum-image displacement along one axis, same operation order on every
 // path that decides coverage (no contraction: see the pragma at use sites).

@@ -113,47 +113,199 @@ __device__ __forceinline__ bool far_from(double dx, double dy, double dz, double
     return fabs(dx) > R + 1.0 || fabs(dy) > R + 1.0 || fabs(dz) > R + 1.0;
 }
 
-// x - box_lo lies in (-n, 2n) because 0 <= x < n and -n <= box_lo < n.
+// x - box_lo lies in (-n, 2n) because 0 <= x < n and -n < box_lo < n.
 __device__ __forceinline__ int box_off(int x, int lo, int n) {
     int d = x - lo;
     d = d < 0 ? d + n : d;
     return d >= n ? d - n : d;
 }
 
+__device__ __forceinline__ bool in_box(const int (&lo)[3], const int (&bn)[3], int x, int y, int z, int nx, int ny,
+                                       int nz) {
+    return box_off(x, lo[0], nx) < bn[0] && box_off(y, lo[1], ny) < bn[1] && box_off(z, lo[2], nz) < bn[2];
+}
 __device__ __forceinline__ bool in_box(const PState& q, int x, int y, int z, int nx, int ny, int nz) {
-    return box_off(x, q.box_lo[0], nx) < q.box_n[0] && box_off(y, q.box_lo[1], ny) < q.box_n[1] &&
-           box_off(z, q.box_lo[2], nz) < q.box_n[2];
+    return in_box(q.box_lo, q.box_n, x, y, z, nx, ny, nz);
+}
+
+// Circular index ranges [a, a + na) and [b, b + nb) modulo n intersect
+// (-n < a, b < n).
+__device__ __forceinline__ bool arcs_meet(int a, int na, int b, int nb, int n) {
+    int ba = b - a, ab = a - b;  // in (-2n, 2n)
+    ba = ba < 0 ? ba + n : ba;
+    ba = ba < 0 ? ba + n : (ba >= n ? ba - n : ba);
+    ab = ab < 0 ? ab + n : ab;
+    ab = ab < 0 ? ab + n : (ab >= n ? ab - n : ab);
+    return ba < na || ab < nb;
 }
 
 template <typename T>
-__device__ __forceinline__ void cell_disp(const Sim<T>& s, int x, int y, int z, const PState& q, double d[3]) {
+__device__ __forceinline__ void cell_disp(const Sim<T>& s, int x, int y, int z, const double (&xc)[3], double d[3]) {
 #pragma clang fp contract(off)
-    d[0] = min_image((double)x + 0.5, q.x[0], (double)s.nx);
-    d[1] = min_image((double)y + 0.5, q.x[1], (double)s.ny);
-    d[2] = min_image((double)z + 0.5, q.x[2], (double)s.nz);
+    d[0] = min_image((double)x + 0.5, xc[0], (double)s.nx);
+    d[1] = min_image((double)y + 0.5, xc[1], (double)s.ny);
+    d[2] = min_image((double)z + 0.5, xc[2], (double)s.nz);
 }
 
-// Box cell t (0 <= t < n0*n1*n2) of particle p -> global coordinates.
-template <typename T>
-__device__ __forceinline__ void box_cell(const Sim<T>& s, const PState& q, int t, int& x, int& y, int& z) {
-    int i = t % q.box_n[0];
-    int j = (t / q.box_n[0]) % q.box_n[1];
-    int k = t / (q.box_n[0] * q.box_n[1]);
-    x = wrapi(q.box_lo[0] + i, s.nx);
-    y = wrapi(q.box_lo[1] + j, s.ny);
-    z = wrapi(q.box_lo[2] + k, s.nz);
-}
+// The fields of one particle a box kernel uses, loaded once into registers.
+struct PLocal {
+    double x[3], v[3], w[3], R, Z, Vp;
+    int lo[3], bn[3], nb, ncell;
+    __device__ __forceinline__ explicit PLocal(const PState& q) {
+        for (int d = 0; d < 3; ++d) {
+            x[d] = q.x[d];
+            v[d] = q.v[d];
+            w[d] = q.w[d];
+            lo[d] = q.box_lo[d];
+            bn[d] = q.box_n[d];
+        }
+        R = q.R;
+        Z = q.Z;
+        Vp = q.Vp;
+        nb = q.nb;
+        ncell = bn[0] * bn[1] * bn[2];
+    }
+};
 
-template <typename T>
-__device__ __forceinline__ bool box_owner_is(const Sim<T>& s, int p, int x, int y, int z) {
-    for (int q = 0; q < p; ++q)
-        if (in_box(s.parts[q], x, y, z, s.nx, s.ny, s.nz)) return false;
-    return true;
-}
+// Box cell t (0 <= t < ncell) -> global coordinates; the divisions by the
+// box extents use multiply-high where the operands allow it.
+struct BoxWalk {
+    int lo[3], bn[3], n01;
+    bool fast;
+    FDiv d0, d01;
+    __device__ __forceinline__ explicit BoxWalk(const PLocal& q)
+        : lo{q.lo[0], q.lo[1], q.lo[2]}, bn{q.bn[0], q.bn[1], q.bn[2]}, n01(q.bn[0] * q.bn[1]),
+          fast((unsigned long long)q.ncell * (unsigned long long)n01 < (1ull << 32) && n01 < (1 << 16)),
+          d0(q.bn[0]), d01(q.bn[0] * q.bn[1] < (1 << 16) ? q.bn[0] * q.bn[1] : 1) {}
+    template <typename T>
+    __device__ __forceinline__ void cell(const Sim<T>& s, int t, int& x, int& y, int& z) const {
+        int q0, k;
+        if (fast) {
+            q0 = d0.div(t);
+            k = d01.div(t);
+        } else {
+            q0 = t / bn[0];
+            k = t / n01;
+        }
+        const int i = t - q0 * bn[0], j = q0 - k * bn[1];
+        x = wrap1(lo[0] + i, s.nx);  // lo + i in (-n, 2n)
+        y = wrap1(lo[1] + j, s.ny);
+        z = wrap1(lo[2] + k, s.nz);
+    }
+};
 
+// Linear index of (x, y, z) with each coordinate in [-n, 2n) (the cells of a
+// box and their neighbours up to distance 2).
 template <typename T>
 __device__ __forceinline__ long cidx(const Sim<T>& s, int x, int y, int z) {
-    return (long)wrapi(x, s.nx) + (long)s.nx * ((long)wrapi(y, s.ny) + (long)s.ny * wrapi(z, s.nz));
+    return (long)wrap1(x, s.nx) + (long)s.nx * ((long)wrap1(y, s.ny) + (long)s.ny * wrap1(z, s.nz));
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour list of a particle's box: the particles (in increasing index,
+// itself included) whose boxes intersect it, with the fields the coverage and
+// ownership tests need, staged in LDS once per workgroup.  Only these can
+// cover a cell of the box or own it first, so every per-cell loop over
+// particles runs over this list; the result is identical to a loop over all
+// particles because the others contribute nothing.  Lists longer than the
+// capacity fall back to reading every particle from global memory.
+// ---------------------------------------------------------------------------
+constexpr int NBR_CAP = 128;
+struct NbrRec {
+    double x[3], R, Z, Vp;  // centre, radius, valency, volume
+    int lo[3], bn[3];
+};
+struct NbrList {
+    int n;  // entries; > NBR_CAP: overflow
+    int idx[NBR_CAP];
+    NbrRec rec[NBR_CAP];
+};
+
+template <typename T>
+__device__ __forceinline__ void build_nbrs(const Sim<T>& s, const PLocal& me, NbrList& L) {
+    __shared__ int wsum[PT / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int total = 0;
+    for (int base = 0; base < s.np; base += PT) {
+        const int k = base + threadIdx.x;
+        bool hit = false;
+        if (k < s.np) {
+            const PState& q = s.parts[k];
+            hit = arcs_meet(me.lo[0], me.bn[0], q.box_lo[0], q.box_n[0], s.nx) &&
+                  arcs_meet(me.lo[1], me.bn[1], q.box_lo[1], q.box_n[1], s.ny) &&
+                  arcs_meet(me.lo[2], me.bn[2], q.box_lo[2], q.box_n[2], s.nz);
+        }
+        const unsigned long long m = __ballot(hit);
+        if (lane == 0) wsum[wave] = __popcll(m);
+        __syncthreads();
+        int off = total, tot = 0;
+        for (int w = 0; w < PT / 64; ++w) {
+            off += w < wave ? wsum[w] : 0;
+            tot += wsum[w];
+        }
+        if (hit) {
+            const int pos = off + __popcll(m & ((1ull << lane) - 1ull));
+            if (pos < NBR_CAP) L.idx[pos] = k;
+        }
+        total += tot;
+        __syncthreads();
+    }
+    if (total <= NBR_CAP) {
+        for (int j = threadIdx.x; j < total; j += PT) {
+            const PState& q = s.parts[L.idx[j]];
+            NbrRec r;
+            for (int d = 0; d < 3; ++d) {
+                r.x[d] = q.x[d];
+                r.lo[d] = q.box_lo[d];
+                r.bn[d] = q.box_n[d];
+            }
+            r.R = q.R;
+            r.Z = q.Z;
+            r.Vp = q.Vp;
+            L.rec[j] = r;
+        }
+    }
+    if (threadIdx.x == 0) L.n = total;
+    __syncthreads();
+}
+
+// Entries of the list (all particles on overflow).
+__device__ __forceinline__ int nbr_count(const NbrList& L, int np) { return L.n > NBR_CAP ? np : L.n; }
+template <typename T>
+__device__ __forceinline__ int nbr_index(const Sim<T>& s, const NbrList& L, int j) {
+    return L.n > NBR_CAP ? j : L.idx[j];
+}
+template <typename T>
+__device__ __forceinline__ NbrRec nbr_rec(const Sim<T>& s, const NbrList& L, int j) {
+    if (L.n <= NBR_CAP) return L.rec[j];
+    const PState& q = s.parts[j];
+    NbrRec r;
+    for (int d = 0; d < 3; ++d) {
+        r.x[d] = q.x[d];
+        r.lo[d] = q.box_lo[d];
+        r.bn[d] = q.box_n[d];
+    }
+    r.R = q.R;
+    r.Z = q.Z;
+    r.Vp = q.Vp;
+    return r;
+}
+
+// Is p the lowest-index particle whose box contains (x, y, z)?  (The cell is
+// in p's box.)
+template <typename T>
+__device__ __forceinline__ bool box_owner_is(const Sim<T>& s, const NbrList& L, int p, int x, int y, int z) {
+    const int n = nbr_count(L, s.np);
+    for (int j = 0; j < n; ++j) {
+        const int k = nbr_index(s, L, j);
+        if (k >= p) break;
+        if (L.n <= NBR_CAP) {
+            if (in_box(L.rec[j].lo, L.rec[j].bn, x, y, z, s.nx, s.ny, s.nz)) return false;
+        } else if (in_box(s.parts[k], x, y, z, s.nx, s.ny, s.nz)) {
+            return false;
+        }
+    }
+    return true;
 }
 
 __device__ __forceinline__ bool stable(uint8_t fl) { return !(fl & (F_CUR | F_PREV | F_WALL)); }
@@ -255,17 +407,20 @@ __global__ void k_move(Sim<T> s, int init) {
 template <typename T>
 __device__ __forceinline__ void geometry_body(const Sim<T>& s, int bx_, int by_, int gx_, int init) {
 #pragma clang fp contract(off)
-    int p = by_;
-    const PState& me = s.parts[p];
-    const int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const int p = by_;
+    const PLocal me(s.parts[p]);
+    const BoxWalk bw(me);
+    __shared__ NbrList L;
+    build_nbrs(s, me, L);
+    const int nn = nbr_count(L, s.np);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int base = bx_ * PT + wave * 64; base < ncell; base += gx_ * PT) {
+    for (int base = bx_ * PT + wave * 64; base < me.ncell; base += gx_ * PT) {
         int t = base + lane;
         int x = 0, y = 0, z = 0;
-        bool active = t < ncell;
+        bool active = t < me.ncell;
         if (active) {
-            box_cell(s, me, t, x, y, z);
-            active = box_owner_is(s, p, x, y, z);
+            bw.cell(s, t, x, y, z);
+            active = box_owner_is(s, L, p, x, y, z);
         }
         long c = active ? cidx(s, x, y, z) : 0;
         uint8_t old = active ? s.flag[c] : 0;
@@ -274,12 +429,13 @@ __device__ __forceinline__ void geometry_body(const Sim<T>& s, int bx_, int by_,
         uint16_t ow = NO_OWNER, pso = NO_OWNER;
         double psum = 0.0;
         double qb = (active && s.wall_charge) ? s.wall_charge[c] : 0.0;
-        for (int k = 0; k < s.np; ++k) {
-            const PState& q = s.parts[k];
-            bool touch = active && in_box(q, x, y, z, s.nx, s.ny, s.nz);
+        for (int j = 0; j < nn; ++j) {
+            const int k = nbr_index(s, L, j);
+            const NbrRec q = nbr_rec(s, L, j);
+            bool touch = active && in_box(q.lo, q.bn, x, y, z, s.nx, s.ny, s.nz);
             double d[3] = {0.0, 0.0, 0.0};
             if (touch) {
-                cell_disp(s, x, y, z, q, d);
+                cell_disp(s, x, y, z, q.x, d);
                 touch = !far_from(d[0], d[1], d[2], q.R);
             }
             double R2 = q.R * q.R;
@@ -334,21 +490,23 @@ __device__ __forceinline__ double rho_abs(const Sim<T>& s, const T* r, int k, lo
 template <typename T>
 __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_, int gx_) {
 #pragma clang fp contract(off)
-    int p = by_;
-    const PState& me = s.parts[p];
-    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const int p = by_;
+    const PLocal me(s.parts[p]);
+    const BoxWalk bw(me);
+    __shared__ NbrList L;
+    build_nbrs(s, me, L);
     T* f = s.f[s.cur];
     const T* rho = s.rho[s.cur];
     // 0-2 Fc, 3-5 Tc, 6..6+MAXS pool, then counts
     double acc[6 + MAXS + 5];
     for (int k = 0; k < 6 + MAXS + 5; ++k) acc[k] = 0.0;
-    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += s.nchunk * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += s.nchunk * PT) {
         int x, y, z;
-        box_cell(s, me, t, x, y, z);
+        bw.cell(s, t, x, y, z);
         long c = cidx(s, x, y, z);
         uint8_t fl = s.flag[c];
         if ((fl & F_CUR) && s.owner[c] == p) acc[6 + MAXS + 3] += 1.0;  // n_b
-        if ((fl & (F_CUR | F_PREV)) && !(fl & F_WALL) && box_owner_is(s, p, x, y, z)) acc[6 + MAXS + 4] += 1.0;
+        if ((fl & (F_CUR | F_PREV)) && !(fl & F_WALL) && box_owner_is(s, L, p, x, y, z)) acc[6 + MAXS + 4] += 1.0;
         if (covered(fl) && s.owner[c] == p) {
             double pf[3] = {0.0, 0.0, 0.0};
             sfor<19>([&](auto I) {
@@ -359,7 +517,7 @@ __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_,
                 pf[2] += fi * q19z(i);
             });
             double r[3];
-            cell_disp(s, x, y, z, me, r);
+            cell_disp(s, x, y, z, me.x, r);
             acc[0] += pf[0];
             acc[1] += pf[1];
             acc[2] += pf[2];
@@ -396,7 +554,7 @@ __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_,
             double base = sizeof(T) == 4 ? 0.0 : 1.0;  // stored density of "no neighbour": 1
             double rbar = nf > 0 ? sum / nf : base;
             double r[3];
-            cell_disp(s, x, y, z, me, r);
+            cell_disp(s, x, y, z, me.x, r);
             double vb[3] = {me.v[0] + (me.w[1] * r[2] - me.w[2] * r[1]),
                             me.v[1] + (me.w[2] * r[0] - me.w[0] * r[2]),
                             me.v[2] + (me.w[0] * r[1] - me.w[1] * r[0])};
@@ -466,16 +624,18 @@ __global__ void k_boundary_reduce(Sim<T> s) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void expel_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    int p = by_;
-    const PState& me = s.parts[p];
-    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const int p = by_;
+    const PLocal me(s.parts[p]);
+    const BoxWalk bw(me);
+    __shared__ NbrList L;
+    build_nbrs(s, me, L);
     T* rho = s.rho[s.cur];
-    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += gx_ * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += gx_ * PT) {
         int x, y, z;
-        box_cell(s, me, t, x, y, z);
+        bw.cell(s, t, x, y, z);
         long n = cidx(s, x, y, z);
         if (!stable(s.flag[n])) continue;
-        if (!box_owner_is(s, p, x, y, z)) continue;
+        if (!box_owner_is(s, L, p, x, y, z)) continue;
         double gain[MAXS] = {0.0, 0.0, 0.0, 0.0};
         bool any = false;
         for (int a = -1; a <= 1; ++a)
@@ -519,13 +679,13 @@ __global__ __launch_bounds__(PT) void k_expel(Sim<T> s) {
 // receives Z / n_b of its particle's charge.
 template <typename T>
 __device__ __forceinline__ void boundary_post_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    int p = by_;
-    const PState& me = s.parts[p];
-    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const int p = by_;
+    const PLocal me(s.parts[p]);
+    const BoxWalk bw(me);
     T* rho = s.rho[s.cur];
-    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += gx_ * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += gx_ * PT) {
         int x, y, z;
-        box_cell(s, me, t, x, y, z);
+        bw.cell(s, t, x, y, z);
         long c = cidx(s, x, y, z);
         uint8_t fl = s.flag[c];
         if (!(fl & F_CUR) || s.owner[c] != p) continue;
@@ -548,16 +708,17 @@ __global__ __launch_bounds__(PT) void k_boundary_post(Sim<T> s) {
 // once when there is none (the usual case).
 template <typename T>
 __device__ __forceinline__ void pool_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    // the usual case, nothing pooled, costs one flag per thread and one barrier
+    bool mine = false;
+    for (int q = threadIdx.x; q < s.np; q += PT) mine |= s.parts[q].npool != 0;
+    if (!__syncthreads_or(mine)) return;
     double pool[MAXS] = {0.0, 0.0, 0.0, 0.0};
     long nflag = 0;
-    bool any = false;
     for (int q = 0; q < s.np; ++q) {
         const PState& pq = s.parts[q];
-        if (pq.npool) any = true;
         for (int k = 0; k < MAXS; ++k) pool[k] += pq.pool[k];
         nflag += pq.nflag;
     }
-    if (!any) return;
     long nS = s.N - s.n_wall - nflag;
     if (nS <= 0) return;
     T* rho = s.rho[s.cur];
@@ -607,18 +768,18 @@ __global__ __launch_bounds__(PT) void k_init_density(Sim<T> s) {
 template <typename T>
 __device__ __forceinline__ void hydro_force_body(const Sim<T>& s, int bx_, int by_, int gx_) {
 #pragma clang fp contract(off)
-    int p = by_;
-    const PState& me = s.parts[p];
-    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const int p = by_;
+    const PLocal me(s.parts[p]);
+    const BoxWalk bw(me);
     const T* f = s.f[s.cur];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += s.nchunk * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += s.nchunk * PT) {
         int x, y, z;
-        box_cell(s, me, t, x, y, z);
+        bw.cell(s, t, x, y, z);
         long b = cidx(s, x, y, z);
         if (!(s.flag[b] & F_CUR) || s.owner[b] != p) continue;
         double r[3];
-        cell_disp(s, x, y, z, me, r);
+        cell_disp(s, x, y, z, me.x, r);
         double vb[3] = {me.v[0] + (me.w[1] * r[2] - me.w[2] * r[1]),
                         me.v[1] + (me.w[2] * r[0] - me.w[0] * r[2]),
                         me.v[2] + (me.w[0] * r[1] - me.w[1] * r[0])};
@@ -656,21 +817,22 @@ __global__ __launch_bounds__(PT) void k_hydro_force(Sim<T> s) {
 template <typename T>
 __device__ __forceinline__ void el_force_body(const Sim<T>& s, int bx_, int by_, int gx_) {
 #pragma clang fp contract(off)
-    int p = by_;
-    const PState& me = s.parts[p];
-    const int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const int p = by_;
+    const PLocal me(s.parts[p]);
+    const BoxWalk bw(me);
+    const int ncell = me.ncell;
     const double R2 = me.R * me.R;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int base = bx_ * PT; base < ncell; base += s.nchunk * PT) {
         int t = base + threadIdx.x;
         int x = 0, y = 0, z = 0;
         bool active = t < ncell;
-        if (active) box_cell(s, me, t, x, y, z);
+        if (active) bw.cell(s, t, x, y, z);
         long c = active ? cidx(s, x, y, z) : 0;
         double qb = 0.0;
         bool need = false;
         double d[3] = {0.0, 0.0, 0.0};
-        if (active) cell_disp(s, x, y, z, me, d);
+        if (active) cell_disp(s, x, y, z, me.x, d);
         if (active && s.charge_mode == EK_CHARGE_UNIFORM) {
             if ((s.flag[c] & F_CUR) && s.owner[c] == p && me.nb > 0) qb = me.Z / (double)me.nb;
         } else if (active) {
@@ -777,13 +939,13 @@ __device__ __forceinline__ int stable19(const Sim<T>& s, int x, int y, int z) {
 
 template <typename T>
 __device__ __forceinline__ void refill_vacated_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    int p = by_;
-    const PState& me = s.parts[p];
-    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const int p = by_;
+    const PLocal me(s.parts[p]);
+    const BoxWalk bw(me);
     T* rho = s.rho[s.cur];
-    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += gx_ * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += gx_ * PT) {
         int x, y, z;
-        box_cell(s, me, t, x, y, z);
+        bw.cell(s, t, x, y, z);
         long v = cidx(s, x, y, z);
         if (!vacated(s.flag[v]) || s.owner_prev[v] != p) continue;
         int nf = stable19(s, x, y, z);
@@ -808,15 +970,17 @@ __global__ __launch_bounds__(PT) void k_refill_vacated(Sim<T> s) {
 
 template <typename T>
 __device__ __forceinline__ void refill_stable_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    int p = by_;
-    const PState& me = s.parts[p];
-    int ncell = me.box_n[0] * me.box_n[1] * me.box_n[2];
+    const int p = by_;
+    const PLocal me(s.parts[p]);
+    const BoxWalk bw(me);
+    __shared__ NbrList L;
+    build_nbrs(s, me, L);
     T* rho = s.rho[s.cur];
-    for (int t = bx_ * PT + threadIdx.x; t < ncell; t += gx_ * PT) {
+    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += gx_ * PT) {
         int x, y, z;
-        box_cell(s, me, t, x, y, z);
+        bw.cell(s, t, x, y, z);
         long n = cidx(s, x, y, z);
-        if (!stable(s.flag[n]) || !box_owner_is(s, p, x, y, z)) continue;
+        if (!stable(s.flag[n]) || !box_owner_is(s, L, p, x, y, z)) continue;
         double share = 0.0;  // sum over vacated neighbours of 1/(N_f(v)+1)
         bool any = false;
         sfor<19>([&](auto I) {

@@ -83,16 +83,6 @@ __device__ __forceinline__ void dft_small(cpx<T> (&v)[R]) {
     }
 }
 
-// Division by a workgroup-uniform divisor 1 <= d <= 2^16 for dividends
-// 0 <= x < 2^16: q = floor(x * ceil(2^32 / d) / 2^32) is exact there (the
-// rounding error of the reciprocal, below x / 2^32, never reaches 1/d).
-struct FDiv {
-    uint32_t m;
-    int d;
-    __device__ __forceinline__ explicit FDiv(int d_) : m(d_ == 1 ? 0u : 0xFFFFFFFFu / (uint32_t)d_ + 1u), d(d_) {}
-    __device__ __forceinline__ int div(int x) const { return d == 1 ? x : (int)__umulhi((uint32_t)x, m); }
-};
-
 // One in-place Stockham stage of radix R over P pencils of length n stored at
 // a[p * ld + index].  Every thread first loads all inputs of its butterflies
 // into registers, the workgroup synchronises, then the outputs are written to
