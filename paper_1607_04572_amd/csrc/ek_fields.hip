@@ -42,6 +42,22 @@ __device__ __forceinline__ long cidx3(const Sim<T>& s, int x, int y, int z) {
     return (long)x + (long)s.nx * ((long)y + (long)s.ny * z);
 }
 
+// 32-bit cell index and element access with a uniform base pointer: every
+// allowed lattice has N * sizeof(T) < 2^32, so the byte offset of a cell fits
+// a 32-bit register and the load/store can use the scalar-base addressing mode.
+template <typename T>
+__device__ __forceinline__ uint32_t cidx32(const Sim<T>& s, int x, int y, int z) {
+    return (uint32_t)x + (uint32_t)s.nx * ((uint32_t)y + (uint32_t)s.ny * (uint32_t)z);
+}
+template <typename T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t e) {
+    return *(const T*)((const char*)base + (uint32_t)(e * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st32_nt(T* __restrict__ base, uint32_t e, T v) {
+    __builtin_nontemporal_store(v, (T*)((char*)base + (uint32_t)(e * (uint32_t)sizeof(T))));
+}
+
 // ---------------------------------------------------------------------------
 // LB cell update (used by the fused EK+LB kernel and the unfused LB kernel)
 // ---------------------------------------------------------------------------
@@ -57,12 +73,12 @@ struct Nbr {
         zp = z == nz - 1 ? 0 : z + 1;
     }
     // source cell r - c_i of population i
+    __device__ __forceinline__ int sx(int i) const { return q19x(i) > 0 ? xm : (q19x(i) < 0 ? xp : x); }
+    __device__ __forceinline__ int sy(int i) const { return q19y(i) > 0 ? ym : (q19y(i) < 0 ? yp : y); }
+    __device__ __forceinline__ int sz(int i) const { return q19z(i) > 0 ? zm : (q19z(i) < 0 ? zp : z); }
     template <typename T>
     __device__ __forceinline__ long src(const Sim<T>& s, int i) const {
-        const int sx = q19x(i) > 0 ? xm : (q19x(i) < 0 ? xp : x);
-        const int sy = q19y(i) > 0 ? ym : (q19y(i) < 0 ? yp : y);
-        const int sz = q19z(i) > 0 ? zm : (q19z(i) < 0 ? zp : z);
-        return cidx3(s, sx, sy, sz);
+        return cidx3(s, sx(i), sy(i), sz(i));
     }
 };
 
@@ -72,7 +88,7 @@ __device__ __forceinline__ void lb_pull(const Sim<T>& s, const Nbr& nb, T (&fi)[
     const T* __restrict__ fs = s.f[s.cur];
     sfor<19>([&](auto I) {
         constexpr int i = I;
-        fi[i] = fs[(long)i * s.N + nb.src<T>(s, i)];
+        fi[i] = ld32(fs + (long)i * s.N, cidx32(s, nb.sx(i), nb.sy(i), nb.sz(i)));
     });
 }
 
@@ -82,7 +98,7 @@ __device__ __forceinline__ unsigned lb_bmask_global(const Sim<T>& s, const Nbr& 
     unsigned bmask = 0;
     sfor<19>([&](auto I) {
         constexpr int i = I;
-        if constexpr (i > 0) bmask |= (unsigned)(s.flag[nb.src<T>(s, i)] & F_CUR) << i;
+        if constexpr (i > 0) bmask |= (unsigned)(ld32(s.flag, cidx32(s, nb.sx(i), nb.sy(i), nb.sz(i))) & F_CUR) << i;
     });
     return bmask;
 }
@@ -90,8 +106,8 @@ __device__ __forceinline__ unsigned lb_bmask_global(const Sim<T>& s, const Nbr& 
 // Stream/collide of fluid cell c with pulled populations fi, force density
 // (fx, fy, fz) and boundary-source mask bmask; writes f* and u.
 template <typename T, bool DEV>
-__device__ __forceinline__ void lb_collide(const Sim<T>& s, long c, const Nbr& nb, T (&fi)[19], unsigned bmask, T fx,
-                                           T fy, T fz) {
+__device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nbr& nb, T (&fi)[19], unsigned bmask,
+                                           T fx, T fy, T fz) {
     const T* __restrict__ fs = s.f[s.cur];
     T* __restrict__ fd = s.f[s.cur ^ 1];
     T* __restrict__ uo = s.u[s.cur ^ 1];
@@ -102,12 +118,11 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, long c, const Nbr& n
             if constexpr (i > 0) {
                 if (bmask & (1u << i)) {
                     // moving bounce-back from the boundary cell b = r - c_i
-                    const long b = nb.src<T>(s, i);
+                    const int bx = nb.sx(i), by = nb.sy(i), bz = nb.sz(i);
                     double vb[3] = {0.0, 0.0, 0.0};
-                    uint16_t ow = s.owner[b];
+                    uint16_t ow = s.owner[cidx3(s, bx, by, bz)];
                     if (ow != NO_OWNER) {
                         const PState& q = s.parts[ow];
-                        const int bx = (int)(b % nx), by = (int)((b / nx) % ny), bz = (int)(b / ((long)nx * ny));
                         double r[3] = {min_image((double)bx + 0.5, q.x[0], (double)nx),
                                        min_image((double)by + 0.5, q.x[1], (double)ny),
                                        min_image((double)bz + 0.5, q.x[2], (double)nz)};
@@ -116,7 +131,7 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, long c, const Nbr& n
                         vb[2] = q.v[2] + (q.w[0] * r[1] - q.w[1] * r[0]);
                     }
                     double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
-                    fi[i] = fs[(long)q19opp(i) * s.N + c] + (T)(6.0 * q19w(i) * cv);
+                    fi[i] = ld32(fs + (long)q19opp(i) * s.N, c) + (T)(6.0 * q19w(i) * cv);
                 }
             }
         });
@@ -146,18 +161,20 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, long c, const Nbr& n
         const T fp = (T)0.5 * (fi[i] + fi[o]);
         const T fm = (T)0.5 * (fi[i] - fi[o]);
         const T delta = (T)3 * w * (cf + (T)1.5 * (g2 * cu * cf - g2 * uf / (T)3));
-        __builtin_nontemporal_store(fi[i] + le * (fp - feq_e) + lo * (fm - feq_o) + delta, &fd[(long)i * s.N + c]);
+        st32_nt(fd + (long)i * s.N, c, fi[i] + le * (fp - feq_e) + lo * (fm - feq_o) + delta);
     });
-    __builtin_nontemporal_store(ux, &uo[c]);
-    __builtin_nontemporal_store(uy, &uo[s.N + c]);
-    __builtin_nontemporal_store(uz, &uo[2 * s.N + c]);
+    st32_nt(uo, c, ux);
+    st32_nt(uo + s.N, c, uy);
+    st32_nt(uo + 2 * s.N, c, uz);
 }
 
 // Velocity of a boundary cell (no populations are streamed there).
 template <typename T>
-__device__ __forceinline__ void lb_wall(const Sim<T>& s, long c) {
+__device__ __forceinline__ void lb_wall(const Sim<T>& s, uint32_t c) {
     T* __restrict__ uo = s.u[s.cur ^ 1];
-    uo[c] = uo[s.N + c] = uo[2 * s.N + c] = (T)0;
+    st32_nt(uo, c, (T)0);
+    st32_nt(uo + s.N, c, (T)0);
+    st32_nt(uo + 2 * s.N, c, (T)0);
 }
 
 // ---------------------------------------------------------------------------
@@ -282,17 +299,18 @@ __device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, T
         int x = wrap1(x0 + i - 1, s.nx), y = wrap1(y0 + j - 1, s.ny);
         x = x < s.nx ? x : s.nx - 1;
         y = y < s.ny ? y : s.ny - 1;
-        long c = cidx3(s, x, y, zz);
+        const uint32_t c = cidx32(s, x, y, zz);
+        const T* __restrict__ ui = s.u[s.cur];
         RecEK<T, NS> r;
 #pragma unroll
-        for (int k = 0; k < NS; ++k) r.v[k] = rin[(long)k * s.N + c];
-        float psi = s.psi[c];
-        uint8_t fl = s.flag[c];
-        r.v[NS] = s.phi[c];
+        for (int k = 0; k < NS; ++k) r.v[k] = ld32(rin + (long)k * s.N, c);
+        float psi = ld32(s.psi, c);
+        uint8_t fl = ld32(s.flag, c);
+        r.v[NS] = ld32(s.phi, c);
         r.v[NS + 1] = (T)psi;
-        r.v[NS + 2] = s.u[s.cur][c];
-        r.v[NS + 3] = s.u[s.cur][s.N + c];
-        r.v[NS + 4] = s.u[s.cur][2 * s.N + c];
+        r.v[NS + 2] = ld32(ui, c);
+        r.v[NS + 3] = ld32(ui + s.N, c);
+        r.v[NS + 4] = ld32(ui + 2 * s.N, c);
         r.v[NS + 5] = (fl & F_CUR) ? (T)1 : (T)0;
 #pragma unroll
         for (int k = NS + 6; k < RecEK<T, NS>::NV; ++k) r.v[k] = (T)0;
@@ -421,7 +439,7 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
         __syncthreads();
         const bool clean = !(sh.dirty[0] | sh.dirty[1] | sh.dirty[2]);
         if (valid) {
-            long c = cidx3(s, x, y, z);
+            const uint32_t c = cidx32(s, x, y, z);
             T dr[NS];
             T fe[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
@@ -438,11 +456,11 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
                 T out;
                 if (wall) out = DEV ? (T)(-s.rho_ref[k]) : (T)0;
                 else out = sh.rec[s0][ctr].r(k) + dr[k];
-                __builtin_nontemporal_store(out, &rout[(long)k * s.N + c]);
+                st32_nt(rout + (long)k * s.N, c, out);
             }
-            __builtin_nontemporal_store(fe[0], &s.fext[c]);
-            __builtin_nontemporal_store(fe[1], &s.fext[s.N + c]);
-            __builtin_nontemporal_store(fe[2], &s.fext[2 * s.N + c]);
+            st32_nt(s.fext, c, fe[0]);
+            st32_nt(s.fext + s.N, c, fe[1]);
+            st32_nt(s.fext + 2 * s.N, c, fe[2]);
             if constexpr (FUSE) {
                 if (wall) {
                     lb_wall(s, c);
@@ -458,28 +476,40 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
     }
 }
 
+// At least two waves per SIMD: keeps the FP64 fused kernel from spilling into
+// accumulation registers past the 256-register budget of that occupancy.
 template <typename T, bool DEV, int NS, int TXW, int TYW, bool FUSE, bool PREFETCH>
-__global__ __launch_bounds__(TXW* TYW) void k_ek(Sim<T> s, int ZC, int gx, int gy, int ntiles) {
+__global__ __launch_bounds__(TXW* TYW) __attribute__((amdgpu_waves_per_eu(2))) void k_ek(Sim<T> s, int ZC, int gx,
+                                                                                          int gy, int ntiles) {
     ek_body<T, DEV, NS, TXW, TYW, FUSE, PREFETCH>(s, blockIdx.x, blockIdx.y, gridDim.x, ZC, gx, gy, ntiles);
 }
 
 // ---------------------------------------------------------------------------
 // LB (unfused kernel)
 // ---------------------------------------------------------------------------
+// Workgroup b covers cells [256 (b mod nbp), 256 (b mod nbp) + 256) of plane
+// z = b div nbp, nbp = ceil(nx ny / 256); the in-plane division by nx is
+// exact by multiply-high (nx ny nx < 2^27).
 template <typename T, bool DEV>
 __device__ __forceinline__ void lb_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    long c = (long)bx_ * BT + threadIdx.x;
-    if (c >= s.N) return;
-    const int nx = s.nx, ny = s.ny;
-    const Nbr nb((int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long)nx * ny)), nx, ny, s.nz);
-    if (s.flag[c] & F_CUR) {
+    const int nx = s.nx, ny = s.ny, P = nx * ny;
+    const int nbp = (P + BT - 1) / BT;
+    const int z = bx_ / nbp;
+    const int cp = (bx_ - z * nbp) * BT + threadIdx.x;
+    if (cp >= P) return;
+    const int y = FDiv(nx).div(cp);
+    const uint32_t c = (uint32_t)z * (uint32_t)P + (uint32_t)cp;
+    const Nbr nb(cp - y * nx, y, z, nx, ny, s.nz);
+    // all loads first (a boundary cell's pulls are wasted, but harmless),
+    // boundary fix-ups (rare) afterwards
+    T fi[19];
+    lb_pull(s, nb, fi);
+    const uint8_t fl = ld32(s.flag, c);
+    const T fx = ld32(s.fext, c), fy = ld32(s.fext + s.N, c), fz = ld32(s.fext + 2 * s.N, c);
+    if (fl & F_CUR) {
         lb_wall(s, c);
         return;
     }
-    // all loads first, boundary fix-ups (rare) afterwards
-    T fi[19];
-    lb_pull(s, nb, fi);
-    const T fx = s.fext[c], fy = s.fext[s.N + c], fz = s.fext[2 * s.N + c];
     lb_collide<T, DEV>(s, c, nb, fi, lb_bmask_global(s, nb), fx, fy, fz);
 }
 
@@ -524,7 +554,7 @@ void launch_fields(const Sim<T>& s, hipStream_t st, hipEvent_t mid) {
     launch_ek<T, kFuseFields<T>>(s, st);
     if (mid) (void)hipEventRecord(mid, st);
     if constexpr (!kFuseFields<T>)
-        hipLaunchKernelGGL((k_lb<T, DEV>), dim3((unsigned)((s.N + BT - 1) / BT)), dim3(BT), 0, st, s);
+        hipLaunchKernelGGL((k_lb<T, DEV>), dim3((unsigned)grids_of<T>(s).n[KK_LB]), dim3(BT), 0, st, s);
 }
 
 // ---------------------------------------------------------------------------

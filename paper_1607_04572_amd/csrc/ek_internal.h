@@ -175,7 +175,7 @@ inline Grids<T> grids_of(const S& s) {
     g.ek_gx = (s.nx + EKTile<T>::TXW - 1) / EKTile<T>::TXW;
     g.ek_gy = (s.ny + EKTile<T>::TYW - 1) / EKTile<T>::TYW;
     g.n[KK_EK] = g.ek_gx * g.ek_gy * ((s.nz + EKTile<T>::ZC - 1) / EKTile<T>::ZC);
-    g.n[KK_LB] = (int)((s.N + 255) / 256);
+    g.n[KK_LB] = ((s.nx * s.ny + 255) / 256) * s.nz;  // whole 256-cell chunks of each z-plane
     return g;
 }
 

@@ -596,10 +596,16 @@ __global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
 // Chunk partials of k_boundary -> particle record, summed in chunk order.
 template <typename T>
 __device__ __forceinline__ void boundary_reduce_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    int p = bx_, k = threadIdx.x;
-    if (k >= 6 + MAXS + 5) return;
+    constexpr int NV = 6 + MAXS + 5;
+    const int p = bx_, k = threadIdx.x;
+    // all chunk partials are fetched at once, then summed in chunk order
+    __shared__ double buf[MAX_CHUNKS][NV];
+    for (int e = threadIdx.x; e < s.nchunk * NV; e += blockDim.x)
+        buf[e / NV][e % NV] = partial_rec(s, PART_BOUNDARY, p, e / NV)[e % NV];
+    __syncthreads();
+    if (k >= NV) return;
     double v = 0.0;
-    for (int c = 0; c < s.nchunk; ++c) v += partial_rec(s, PART_BOUNDARY, p, c)[k];
+    for (int c = 0; c < s.nchunk; ++c) v += buf[c][k];
     PState& me = s.parts[p];
     if (k < 3) me.Fc[k] = v;
     else if (k < 6) me.Tc[k - 3] = v;
@@ -879,11 +885,16 @@ __device__ __forceinline__ void finish_body(const Sim<T>& s, int bx_, int by_, i
 #pragma clang fp contract(off)
     const int p = bx_, k = threadIdx.x;
     __shared__ double sum[12];
+    // all chunk partials are fetched at once, then summed in chunk order
+    __shared__ double buf[MAX_CHUNKS][12];
+    for (int e = threadIdx.x; e < s.nchunk * 12; e += blockDim.x) {
+        const int c = e / 12, q = e % 12;
+        buf[c][q] = partial_rec(s, q < 6 ? PART_HYDRO : PART_EL, p, c)[q < 6 ? q : q - 6];
+    }
+    __syncthreads();
     if (k < 12) {
-        const int kind = k < 6 ? PART_HYDRO : PART_EL;
-        const int j = k < 6 ? k : k - 6;
         double v = 0.0;
-        for (int c = 0; c < s.nchunk; ++c) v += partial_rec(s, kind, p, c)[j];
+        for (int c = 0; c < s.nchunk; ++c) v += buf[c][k];
         sum[k] = v;
     }
     __syncthreads();
