@@ -158,6 +158,16 @@ __device__ __forceinline__ void fft_lds(cpx<T>* a, int n, int P, int ld, const c
     }
 }
 
+// The twiddle table of one axis (n entries) is staged in LDS behind the pencil
+// data, so that the stages read it at LDS latency.
+template <typename T>
+__device__ __forceinline__ const cpx<T>* stage_twiddles(cpx<T>* a, int data_elems, const T* tw, int n) {
+    cpx<T>* t = a + data_elems;
+    const cpx<T>* g = reinterpret_cast<const cpx<T>*>(tw);
+    for (int m = threadIdx.x; m < n; m += FT) t[m] = g[m];
+    return t;
+}
+
 // ---------------------------------------------------------------------------
 // Pass X (forward): charge assembly + two-for-one real FFT along x.
 // Work item: a pair of rows (y, y+1) at one z.  P pairs per workgroup.
@@ -171,6 +181,7 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
     const int pair0 = bx_ * P;
     const T* rho = s.rho[s.cur];
     const FDiv dn(n), dnh(s.nxh);
+    const cpx<T>* tw = stage_twiddles<T>(a, P * ld, s.tw[0], n);
     for (int t = threadIdx.x; t < P * n; t += FT) {
         int pen = dn.div(t), x = t - pen * n;
         int pr = pair0 + pen;
@@ -189,7 +200,7 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
         a[pen * ld + x] = v;
     }
     __syncthreads();
-    fft_lds<T, false>(a, n, P, ld, reinterpret_cast<const cpx<T>*>(s.tw[0]));
+    fft_lds<T, false>(a, n, P, ld, tw);
     const cpx<T>* r = a;
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
     const int nh = s.nxh;
@@ -226,6 +237,7 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
     const int pair0 = bx_ * P;
     const cpx<T>* S = reinterpret_cast<const cpx<T>*>(s.spec);
     const FDiv dn(n);
+    const cpx<T>* tw = stage_twiddles<T>(a, P * ld, s.tw[0], n);
     for (int t = threadIdx.x; t < P * n; t += FT) {
         int pen = dn.div(t), k = t - pen * n;
         int pr = pair0 + pen;
@@ -243,7 +255,7 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
         a[pen * ld + k] = v;
     }
     __syncthreads();
-    fft_lds<T, true>(a, n, P, ld, reinterpret_cast<const cpx<T>*>(s.tw[0]));
+    fft_lds<T, true>(a, n, P, ld, tw);
     for (int t = threadIdx.x; t < P * n; t += FT) {
         int pen = dn.div(t), x = t - pen * n;
         int pr = pair0 + pen;
@@ -271,19 +283,21 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int by_, in
     int tiles = (nh + TX - 1) / TX;
     int z = bx_ / tiles;
     int kx0 = (bx_ - z * tiles) * TX;
+    // columns of this tile: TX, fewer in the last one (the Nyquist column alone
+    // when nh = n/2 + 1 is one more than a multiple of TX)
+    const int TC = nh - kx0 < TX ? nh - kx0 : TX;
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec) + (long)z * n * nh;
-    const FDiv dtx(TX);
-    for (int t = threadIdx.x; t < TX * n; t += FT) {
-        int y = dtx.div(t), i = t - y * TX;
-        int kx = kx0 + i;
-        a[i * ld + y] = kx < nh ? S[(long)y * nh + kx] : mk<T>(0, 0);
+    const FDiv dtc(TC);
+    const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[1], n);
+    for (int t = threadIdx.x; t < TC * n; t += FT) {
+        int y = dtc.div(t), i = t - y * TC;
+        a[i * ld + y] = S[(long)y * nh + kx0 + i];
     }
     __syncthreads();
-    fft_lds<T, INV>(a, n, TX, ld, reinterpret_cast<const cpx<T>*>(s.tw[1]));
-    for (int t = threadIdx.x; t < TX * n; t += FT) {
-        int y = dtx.div(t), i = t - y * TX;
-        int kx = kx0 + i;
-        if (kx < nh) S[(long)y * nh + kx] = a[i * ld + y];
+    fft_lds<T, INV>(a, n, TC, ld, tw);
+    for (int t = threadIdx.x; t < TC * n; t += FT) {
+        int y = dtc.div(t), i = t - y * TC;
+        S[(long)y * nh + kx0 + i] = a[i * ld + y];
     }
 }
 
@@ -303,34 +317,31 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
     int tiles = (nh + TX - 1) / TX;
     int ky = bx_ / tiles;
     int kx0 = (bx_ - ky * tiles) * TX;
+    const int TC = nh - kx0 < TX ? nh - kx0 : TX;  // columns of this tile
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
     const long zstride = (long)ny * nh;
-    const FDiv dtx(TX), dn(n);
-    for (int t = threadIdx.x; t < TX * n; t += FT) {
-        int z = dtx.div(t), i = t - z * TX;
-        int kx = kx0 + i;
-        a[i * ld + z] = kx < nh ? S[z * zstride + (long)ky * nh + kx] : mk<T>(0, 0);
+    const FDiv dtc(TC), dn(n);
+    const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[2], n);
+    for (int t = threadIdx.x; t < TC * n; t += FT) {
+        int z = dtc.div(t), i = t - z * TC;
+        a[i * ld + z] = S[z * zstride + (long)ky * nh + kx0 + i];
     }
     __syncthreads();
-    fft_lds<T, false>(a, n, TX, ld, reinterpret_cast<const cpx<T>*>(s.tw[2]));
+    fft_lds<T, false>(a, n, TC, ld, tw);
     const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
-    for (int t = threadIdx.x; t < TX * n; t += FT) {
+    for (int t = threadIdx.x; t < TC * n; t += FT) {
         int i = dn.div(t), kz = t - i * n;
         int kx = kx0 + i;
-        T g = 0;
-        if (kx < nh) {
-            T K2 = s.k2[0][kx] + s.k2[1][ky] + s.k2[2][kz];
-            g = (kx == 0 && ky == 0 && kz == 0) ? (T)0 : scale / K2;
-        }
+        T K2 = s.k2[0][kx] + s.k2[1][ky] + s.k2[2][kz];
+        T g = (kx == 0 && ky == 0 && kz == 0) ? (T)0 : scale / K2;
         cpx<T> v = a[i * ld + kz];
         a[i * ld + kz] = mk<T>(v.x * g, v.y * g);
     }
     __syncthreads();
-    fft_lds<T, true>(a, n, TX, ld, reinterpret_cast<const cpx<T>*>(s.tw[2]));
-    for (int t = threadIdx.x; t < TX * n; t += FT) {
-        int z = dtx.div(t), i = t - z * TX;
-        int kx = kx0 + i;
-        if (kx < nh) S[z * zstride + (long)ky * nh + kx] = a[i * ld + z];
+    fft_lds<T, true>(a, n, TC, ld, tw);
+    for (int t = threadIdx.x; t < TC * n; t += FT) {
+        int z = dtc.div(t), i = t - z * TC;
+        S[z * zstride + (long)ky * nh + kx0 + i] = a[i * ld + z];
     }
 }
 
@@ -344,12 +355,12 @@ void launch_charge_poisson(const Sim<T>& s, hipStream_t st) {
     const size_t cs = sizeof(cpx<T>);
     Grids<T> g = grids_of<T>(s);
     int P = fft_pencils_x(s.nx);
-    size_t shx = (size_t)P * (s.nx + 1) * cs;
+    size_t shx = ((size_t)P * (s.nx + 1) + s.nx) * cs;
     hipLaunchKernelGGL(k_fft_x_fwd<T>, dim3(g.n[KK_FFTX]), dim3(FT), shx, st, s, P);
     int TXy = fft_tile_kx(s.ny, sizeof(T)), TXz = fft_tile_kx(s.nz, sizeof(T));
-    size_t shy = (size_t)TXy * (s.ny + 1) * cs;
+    size_t shy = ((size_t)TXy * (s.ny + 1) + s.ny) * cs;
     hipLaunchKernelGGL((k_fft_y<T, false>), dim3(g.n[KK_FFTY]), dim3(FT), shy, st, s, TXy);
-    size_t shz = (size_t)TXz * (s.nz + 1) * cs;
+    size_t shz = ((size_t)TXz * (s.nz + 1) + s.nz) * cs;
     hipLaunchKernelGGL(k_fft_z_green<T>, dim3(g.n[KK_FFTZ]), dim3(FT), shz, st, s, TXz);
     hipLaunchKernelGGL((k_fft_y<T, true>), dim3(g.n[KK_FFTY]), dim3(FT), shy, st, s, TXy);
     hipLaunchKernelGGL(k_fft_x_inv<T>, dim3(g.n[KK_FFTX]), dim3(FT), shx, st, s, P);
@@ -364,7 +375,7 @@ constexpr int BATCH_FFT_BLOCKS = 2048;
 static size_t batch_lds_x() {
     size_t m = 0;
     for (int n = 8; n <= MAX_FFT; n += 2) {
-        size_t v = (size_t)fft_pencils_x(n) * (n + 1) * sizeof(cpx<float>);
+        size_t v = ((size_t)fft_pencils_x(n) * (n + 1) + n) * sizeof(cpx<float>);
         m = v > m ? v : m;
     }
     return m;
@@ -372,7 +383,7 @@ static size_t batch_lds_x() {
 static size_t batch_lds_yz() {
     size_t m = 0;
     for (int n = 8; n <= MAX_FFT; n += 2) {
-        size_t v = (size_t)fft_tile_kx(n, 4) * (n + 1) * sizeof(cpx<float>);
+        size_t v = ((size_t)fft_tile_kx(n, 4) * (n + 1) + n) * sizeof(cpx<float>);
         m = v > m ? v : m;
     }
     return m;
