@@ -134,7 +134,8 @@ def make_params(nx, ny, nz, nu, kT, lambda_B, E, species, partial_volume=True,
 
 
 def make_particles(specs) -> C.Array:
-    """specs: list of dicts with x, R, Z, M and optional v, w, mode."""
+    """specs: list of dicts with x, R, Z, M and optional v, w, mode, and the
+    force F and torque T of the last completed step (0 by default)."""
     arr = (OrParticle * max(1, len(specs)))()
     for k, s in enumerate(specs):
         q = arr[k]
@@ -142,7 +143,8 @@ def make_particles(specs) -> C.Array:
             q.x[dd] = s["x"][dd]
             q.v[dd] = s.get("v", (0, 0, 0))[dd]
             q.w[dd] = s.get("w", (0, 0, 0))[dd]
-            q.F[dd] = q.T[dd] = 0.0
+            q.F[dd] = s.get("F", (0, 0, 0))[dd]
+            q.T[dd] = s.get("T", (0, 0, 0))[dd]
         q.R, q.Z, q.M = s["R"], s["Z"], s["M"]
         q.mode = int(s.get("mode", 0))
     return arr
@@ -208,6 +210,39 @@ class OracleSim:
         self.phi = np.zeros(N)
         self.step_count = 0
         self.last = {}
+
+    @classmethod
+    def from_state(cls, params: OrParams, particles: list, f: np.ndarray, rho: np.ndarray, u: np.ndarray,
+                   flag: np.ndarray, owner: np.ndarray) -> "OracleSim":
+        """A simulation resumed at a step boundary from a given state: the
+        populations, solute densities, fluid velocity of the last LB update,
+        boundary flags and owners (which the next step's moving-boundary
+        update compares against), and the particles (with v, w and the F, T
+        of the last step).  Partial volumes, particle charge, potential and
+        coupling force are recomputed by the next step."""
+        self = cls.__new__(cls)
+        self.L = lib()
+        self.p = params
+        self.nx, self.ny, self.nz = params.nx, params.ny, params.nz
+        self.N = N = self.nx * self.ny * self.nz
+        self.ns = params.n_species
+        self.np = len(particles)
+        self.pt = make_particles(particles)
+        self.static_mask = None
+        self.static_charge = None
+        self.flag = np.ascontiguousarray(flag, dtype=np.uint8).reshape(-1).copy()
+        self.owner = np.ascontiguousarray(owner, dtype=np.int32).reshape(-1).copy()
+        self.psi = np.zeros(N)
+        self.rhob = np.zeros(N)
+        self.f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1).copy()
+        self.rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1).copy()
+        self.u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1).copy()
+        assert self.f.size == 19 * N and self.rho.size == self.ns * N and self.u.size == 3 * N
+        self.fext = np.zeros(3 * N)
+        self.phi = np.zeros(N)
+        self.step_count = 0
+        self.last = {}
+        return self
 
     # -- phases --------------------------------------------------------------
     def geometry(self, flag, owner, psi, rhob):
