@@ -13,7 +13,10 @@ before the timed region.
 One JSON line is printed with the contract fields plus:
   roofline      -- the dominant kernel (LB stream/collide): algorithmic bytes
                    per launch / its mean duration from HIP events on the
-                   library's stream, against the 8 TB/s HBM peak;
+                   library's stream, against the 8 TB/s HBM peak; traffic =
+                   HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE
+                   counter passes stored by paper_1607_04572_amd/counters.py,
+                   null once the kernel's sources differ from the measured ones;
   cpu_baseline  -- the FP64 CPU oracle timed on one step of the same workload;
   kernels       -- per-stage mean times and algorithmic-byte bandwidths;
   fp64_plain    -- the same workload in FP64;
@@ -161,6 +164,9 @@ def main():
         ms = stages[st]
         kern[st] = {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9, "bytes_per_cell": algorithmic_bytes(st, w32, 4)}
     fk = kern["lb"]
+    from paper_1607_04572_amd import counters
+    meas = counters.stored_traffic()
+    lb_bytes = fk["bytes_per_cell"] * w32.cells
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
@@ -171,8 +177,10 @@ def main():
                    "scheme": "partial volume", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_lb (stream/collide)",
                      "achieved": fk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": fk["GBps"] / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": fk["bytes_per_cell"] * w32.cells, "launch_ms": fk["ms"]},
+                     "frac": fk["GBps"] / HBM_PEAK_GBS,
+                     "traffic": meas["traffic_bytes_per_launch"] if meas else None,
+                     "traffic_over_algorithmic": meas["traffic_bytes_per_launch"] / lb_bytes if meas else None,
+                     "bytes_per_launch": lb_bytes, "launch_ms": fk["ms"]},
         "kernels": {"stage_ms": stages, **{k: v for k, v in kern.items()}},
         "diagnostics": {"species_total": [float(x) for x in diag["species_total"][:len(w32.species)]],
                         "max_velocity": diag["max_velocity"]},

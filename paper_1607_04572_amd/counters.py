@@ -1,0 +1,91 @@
+"""HBM traffic of the dominant kernel from hardware counters.
+
+Two counter passes of the same short bench run (each its own rocprofv3
+process), FETCH_SIZE and WRITE_SIZE in KiB per dispatch, are scaled by what the
+same counters read for the plain copy kernel of known size that the run also
+launches (bench.py --copy-probe-mib).  The result is stored in counters.json
+next to this file together with a hash of the kernel's sources; bench.py reports
+it only while the sources still match (otherwise the counters describe a kernel
+that no longer exists and the traffic is reported as null).
+
+Usage, from the repository root (cd /tmp && export TMPDIR=/tmp first):
+
+  rocprofv3 --pmc FETCH_SIZE -d OUT/pmc_fetch -o run -- python <repo>/bench.py \\
+      --steps 6 --warmup 2 --profile-steps 2 --no-cpu-baseline --no-fp64 --no-serve --copy-probe-mib 1024
+  rocprofv3 --pmc WRITE_SIZE -d OUT/pmc_write -o run -- python <repo>/bench.py (same flags)
+  python -m paper_1607_04572_amd.counters OUT/pmc_fetch/run_results.db OUT/pmc_write/run_results.db 1024
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+STORE = os.path.join(HERE, "counters.json")
+KERNEL = "k_lb<float, true>"
+SOURCES = ["csrc/ek_lb.h", "csrc/ek_lb.hip", "csrc/ek_internal.h"]
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for s in SOURCES:
+        with open(os.path.join(HERE, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def per_dispatch(db: str, counter: str) -> dict:
+    """Mean value of one counter per kernel (summed over instances of a dispatch)."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
+                     "where counter_name = ? group by dispatch_id", (counter,)).fetchall()
+    acc: dict = {}
+    for name, _, v in rows:
+        acc.setdefault(name, []).append(v)
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def pick(d: dict, key: str) -> float:
+    hits = [v for k, v in d.items() if key in k]
+    if not hits:
+        raise KeyError(f"no dispatch of {key} in the counter data")
+    return hits[0]
+
+
+def main(fetch_db: str, write_db: str, copy_mib: int) -> dict:
+    fetch = per_dispatch(fetch_db, "FETCH_SIZE")
+    write = per_dispatch(write_db, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    f_copy, w_copy = pick(fetch, "k_copy16"), pick(write, "k_copy16")
+    f_scale, w_scale = copy_kib / f_copy, copy_kib / w_copy
+    f_lb, w_lb = pick(fetch, KERNEL), pick(write, KERNEL)
+    out = {
+        "kernel": KERNEL,
+        "source_sha256": source_hash(),
+        "fetch_kib_per_dispatch": f_lb, "write_kib_per_dispatch": w_lb,
+        "copy_probe_mib": copy_mib, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+        "fetch_scale": f_scale, "write_scale": w_scale,
+        "traffic_bytes_per_launch": (f_lb * f_scale + w_lb * w_scale) * 1024.0,
+        "read_bytes_per_launch": f_lb * f_scale * 1024.0, "write_bytes_per_launch": w_lb * w_scale * 1024.0,
+        "all_kernels_fetch_kib": fetch, "all_kernels_write_kib": write,
+    }
+    with open(STORE, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+def stored_traffic() -> dict | None:
+    """The stored measurement if it describes the current sources, else None."""
+    if not os.path.exists(STORE):
+        return None
+    with open(STORE) as f:
+        d = json.load(f)
+    return d if d.get("source_sha256") == source_hash() else None
+
+
+if __name__ == "__main__":
+    r = main(sys.argv[1], sys.argv[2], int(sys.argv[3]))
+    print(json.dumps({k: v for k, v in r.items() if not k.startswith("all_")}, indent=1))

@@ -1,4 +1,6 @@
-// ek_fields.hip -- the full-lattice stencil kernels of a step.
+// ek_fields.hip -- the EK solute update of a step, alone (FP32 path; the LB
+// stream/collide then runs as its own kernel, ek_lb.hip) or fused with the LB
+// cell update of ek_lb.h (FP64 path).
 //
 // k_ek: Nernst-Planck solute update (Sec. III.C, III.D.2).  For each cell, the
 //   flux on each of its 26 links is evaluated (13 directions, both ends), the
@@ -15,167 +17,16 @@
 //     zero if either end is a boundary cell.
 //   The staged neighbourhood lives in LDS: a (TX+2) x (TY+2) x 3 window of every
 //   input field, marched along z.
-//
-// k_lb: D3Q19 TRT stream/collide with the Guo force (Sec. III.A), pull form:
-//   f_i(r) <- f_i*(r - c_i), or, if r - c_i is a boundary cell, the moving
-//   bounce-back f_ibar*(r) + 6 w_i rho0 c_i.v_b (Sec. III.A/B).  Then
-//   rho = sum f_i, j = sum f_i c_i, u = j + f/2,
-//   f_i* = f_i + le (f_i+ - feq_i+) + lo (f_i- - feq_i-) + Delta_i,
-//   feq_i+ = w_i (rho + 9/2 (c.u)^2 - 3/2 u^2),  feq_i- = 3 w_i c.j,
-//   Delta_i = 3 w_i [c.f + 3/2 (2+le)((c.u)(c.f) - u.f/3)].
-// k_ek<..., FUSE>: both in one pass (used for FP64): each thread finishes its
-//   cell's EK update and then streams/collides the same cell with the coupling
-//   force still in registers.  The velocity is double-buffered (EK reads
-//   u[cur], LB writes u[cur^1]) so that the two can interleave across
-//   workgroups.
-// On the FP32 path populations are stored as f_i - w_i and densities as
-// rho_k - mean_k; every formula above is linear in those offsets except the
-// explicit mean terms, which are carried exactly.
-#include "ek_internal.h"
+// k_ek<..., FUSE>: EK and LB in one pass: each thread finishes its cell's EK
+//   update and then streams/collides the same cell with the coupling force
+//   still in registers.  The velocity is double-buffered (EK reads u[cur], LB
+//   writes u[cur^1]) so that the two can interleave across workgroups.
+// On the FP32 path densities are stored as rho_k - mean_k; every formula above
+// is linear in those offsets except the explicit mean terms, which are carried
+// exactly.
+#include "ek_lb.h"
 
 namespace ek {
-
-constexpr int BT = 256;
-
-template <typename T>
-__device__ __forceinline__ long cidx3(const Sim<T>& s, int x, int y, int z) {
-    return (long)x + (long)s.nx * ((long)y + (long)s.ny * z);
-}
-
-// 32-bit cell index and element access with a uniform base pointer: every
-// allowed lattice has N * sizeof(T) < 2^32, so the byte offset of a cell fits
-// a 32-bit register and the load/store can use the scalar-base addressing mode.
-template <typename T>
-__device__ __forceinline__ uint32_t cidx32(const Sim<T>& s, int x, int y, int z) {
-    return (uint32_t)x + (uint32_t)s.nx * ((uint32_t)y + (uint32_t)s.ny * (uint32_t)z);
-}
-template <typename T>
-__device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t e) {
-    return *(const T*)((const char*)base + (uint32_t)(e * (uint32_t)sizeof(T)));
-}
-template <typename T>
-__device__ __forceinline__ void st32_nt(T* __restrict__ base, uint32_t e, T v) {
-    __builtin_nontemporal_store(v, (T*)((char*)base + (uint32_t)(e * (uint32_t)sizeof(T))));
-}
-
-// ---------------------------------------------------------------------------
-// LB cell update (used by the fused EK+LB kernel and the unfused LB kernel)
-// ---------------------------------------------------------------------------
-// Periodic neighbour coordinates of one cell.
-struct Nbr {
-    int x, y, z, xm, xp, ym, yp, zm, zp;
-    __device__ __forceinline__ Nbr(int x_, int y_, int z_, int nx, int ny, int nz) : x(x_), y(y_), z(z_) {
-        xm = x == 0 ? nx - 1 : x - 1;
-        xp = x == nx - 1 ? 0 : x + 1;
-        ym = y == 0 ? ny - 1 : y - 1;
-        yp = y == ny - 1 ? 0 : y + 1;
-        zm = z == 0 ? nz - 1 : z - 1;
-        zp = z == nz - 1 ? 0 : z + 1;
-    }
-    // source cell r - c_i of population i
-    __device__ __forceinline__ int sx(int i) const { return q19x(i) > 0 ? xm : (q19x(i) < 0 ? xp : x); }
-    __device__ __forceinline__ int sy(int i) const { return q19y(i) > 0 ? ym : (q19y(i) < 0 ? yp : y); }
-    __device__ __forceinline__ int sz(int i) const { return q19z(i) > 0 ? zm : (q19z(i) < 0 ? zp : z); }
-    template <typename T>
-    __device__ __forceinline__ long src(const Sim<T>& s, int i) const {
-        return cidx3(s, sx(i), sy(i), sz(i));
-    }
-};
-
-// Pull every population from its source r - c_i (independent loads).
-template <typename T>
-__device__ __forceinline__ void lb_pull(const Sim<T>& s, const Nbr& nb, T (&fi)[19]) {
-    const T* __restrict__ fs = s.f[s.cur];
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        fi[i] = ld32(fs + (long)i * s.N, cidx32(s, nb.sx(i), nb.sy(i), nb.sz(i)));
-    });
-}
-
-// Boundary-cell sources (bit i of bmask: r - c_i is a boundary cell).
-template <typename T>
-__device__ __forceinline__ unsigned lb_bmask_global(const Sim<T>& s, const Nbr& nb) {
-    unsigned bmask = 0;
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        if constexpr (i > 0) bmask |= (unsigned)(ld32(s.flag, cidx32(s, nb.sx(i), nb.sy(i), nb.sz(i))) & F_CUR) << i;
-    });
-    return bmask;
-}
-
-// Stream/collide of fluid cell c with pulled populations fi, force density
-// (fx, fy, fz) and boundary-source mask bmask; writes f* and u.
-template <typename T, bool DEV>
-__device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nbr& nb, T (&fi)[19], unsigned bmask,
-                                           T fx, T fy, T fz) {
-    const T* __restrict__ fs = s.f[s.cur];
-    T* __restrict__ fd = s.f[s.cur ^ 1];
-    T* __restrict__ uo = s.u[s.cur ^ 1];
-    if (bmask) {
-        const int nx = s.nx, ny = s.ny, nz = s.nz;
-        sfor<19>([&](auto I) {
-            constexpr int i = I;
-            if constexpr (i > 0) {
-                if (bmask & (1u << i)) {
-                    // moving bounce-back from the boundary cell b = r - c_i
-                    const int bx = nb.sx(i), by = nb.sy(i), bz = nb.sz(i);
-                    double vb[3] = {0.0, 0.0, 0.0};
-                    uint16_t ow = s.owner[cidx3(s, bx, by, bz)];
-                    if (ow != NO_OWNER) {
-                        const PState& q = s.parts[ow];
-                        double r[3] = {min_image((double)bx + 0.5, q.x[0], (double)nx),
-                                       min_image((double)by + 0.5, q.x[1], (double)ny),
-                                       min_image((double)bz + 0.5, q.x[2], (double)nz)};
-                        vb[0] = q.v[0] + (q.w[1] * r[2] - q.w[2] * r[1]);
-                        vb[1] = q.v[1] + (q.w[2] * r[0] - q.w[0] * r[2]);
-                        vb[2] = q.v[2] + (q.w[0] * r[1] - q.w[1] * r[0]);
-                    }
-                    double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
-                    fi[i] = ld32(fs + (long)q19opp(i) * s.N, c) + (T)(6.0 * q19w(i) * cv);
-                }
-            }
-        });
-    }
-    T rho = (T)0, jx = (T)0, jy = (T)0, jz = (T)0;
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        rho += fi[i];
-        if constexpr (q19x(i) != 0) jx += (T)q19x(i) * fi[i];
-        if constexpr (q19y(i) != 0) jy += (T)q19y(i) * fi[i];
-        if constexpr (q19z(i) != 0) jz += (T)q19z(i) * fi[i];
-    });
-    const T ux = jx + (T)0.5 * fx, uy = jy + (T)0.5 * fy, uz = jz + (T)0.5 * fz;
-    const T usq = ux * ux + uy * uy + uz * uz;
-    const T uf = ux * fx + uy * fy + uz * fz;
-    const T le = s.lam_e, lo = s.lam_o;
-    const T g2 = (T)2 + le;
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        constexpr int o = q19opp(i);
-        const T w = (T)q19w(i);
-        const T cu = (T)q19x(i) * ux + (T)q19y(i) * uy + (T)q19z(i) * uz;
-        const T cj = (T)q19x(i) * jx + (T)q19y(i) * jy + (T)q19z(i) * jz;
-        const T cf = (T)q19x(i) * fx + (T)q19y(i) * fy + (T)q19z(i) * fz;
-        const T feq_e = w * (rho + (T)4.5 * cu * cu - (T)1.5 * usq);
-        const T feq_o = w * (T)3 * cj;
-        const T fp = (T)0.5 * (fi[i] + fi[o]);
-        const T fm = (T)0.5 * (fi[i] - fi[o]);
-        const T delta = (T)3 * w * (cf + (T)1.5 * (g2 * cu * cf - g2 * uf / (T)3));
-        st32_nt(fd + (long)i * s.N, c, fi[i] + le * (fp - feq_e) + lo * (fm - feq_o) + delta);
-    });
-    st32_nt(uo, c, ux);
-    st32_nt(uo + s.N, c, uy);
-    st32_nt(uo + 2 * s.N, c, uz);
-}
-
-// Velocity of a boundary cell (no populations are streamed there).
-template <typename T>
-__device__ __forceinline__ void lb_wall(const Sim<T>& s, uint32_t c) {
-    T* __restrict__ uo = s.u[s.cur ^ 1];
-    st32_nt(uo, c, (T)0);
-    st32_nt(uo + s.N, c, (T)0);
-    st32_nt(uo + 2 * s.N, c, (T)0);
-}
 
 // ---------------------------------------------------------------------------
 // EK
@@ -276,12 +127,40 @@ __device__ __forceinline__ void link_flux(const Sim<T>& s, const RecEK<T, NS>& a
 }
 
 // LDS window: (TXW+2) x (TYW+2) records for three consecutive z-planes
-// (z-1, z, z+1), marched along z.
+// (z-1, z, z+1), marched along z.  A record is stored as NCH 16-byte chunks,
+// chunk-major (ch[slot][j][cell]): the lanes of a wavefront reading the same
+// chunk of consecutive cells touch consecutive 16-byte words, free of bank
+// conflicts, where whole records side by side would be read at a stride.
 template <typename T, int NS, int TXW, int TYW>
 struct EKShared {
     static constexpr int WX = TXW + 2, WY = TYW + 2, WPL = WX * WY;
-    RecEK<T, NS> rec[3][WPL];
+    static constexpr int PER = 16 / sizeof(T);                 // elements per chunk
+    static constexpr int NCH = RecEK<T, NS>::NV / PER;         // chunks per record
+    struct alignas(16) Chunk { T v[PER]; };
+    Chunk ch[3][NCH][WPL];
     int dirty[3];
+    __device__ __forceinline__ RecEK<T, NS> get(int slot, int i) const {
+        RecEK<T, NS> r;
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            const Chunk c = ch[slot][j][i];
+#pragma unroll
+            for (int e = 0; e < PER; ++e) r.v[j * PER + e] = c.v[e];
+        }
+        return r;
+    }
+    __device__ __forceinline__ void put(int slot, int i, const RecEK<T, NS>& r) {
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            Chunk c;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) c.v[e] = r.v[j * PER + e];
+            ch[slot][j][i] = c;
+        }
+    }
+    // one element of a record (reads only its chunk)
+    __device__ __forceinline__ T elem(int slot, int i, int k) const { return ch[slot][k / PER][i].v[k % PER]; }
+    __device__ __forceinline__ bool wall(int slot, int i) const { return elem(slot, i, NS + 5) != (T)0; }
 };
 
 // Load one plane; returns whether it holds a boundary cell or a partial volume.
@@ -314,7 +193,7 @@ __device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, T
         r.v[NS + 5] = (fl & F_CUR) ? (T)1 : (T)0;
 #pragma unroll
         for (int k = NS + 6; k < RecEK<T, NS>::NV; ++k) r.v[k] = (T)0;
-        sh.rec[slot][t] = r;
+        sh.put(slot, t, r);
         dirty |= (psi != 0.0f) || (fl & F_CUR);
     }
     return dirty;
@@ -334,15 +213,15 @@ template <typename T, bool DEV, int NS, int TXW, int TYW, bool CLEAN>
 __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T, NS, TXW, TYW>& sh, int s0, int sm,
                                                int sp, int ctr, const EKConst<T, NS>& K, T (&dr)[NS], T (&fe)[3]) {
     using SH = EKShared<T, NS, TXW, TYW>;
-    const RecEK<T, NS> me = sh.rec[s0][ctr];
+    const RecEK<T, NS> me = sh.get(s0, ctr);
     sfor<13>([&](auto HH) {
         constexpr int h = HH;
         constexpr int ox = hx(h), oy = hy(h), oz = hz(h);
         const int up = ctr + oy * SH::WX + ox, dn = ctr - oy * SH::WX - ox;
         const int sup = oz == 0 ? s0 : (oz > 0 ? sp : sm);
         const int sdn = oz == 0 ? s0 : (oz > 0 ? sm : sp);
-        const RecEK<T, NS> cu = sh.rec[sup][up];
-        const RecEK<T, NS> cd = sh.rec[sdn][dn];
+        const RecEK<T, NS> cu = sh.get(sup, up);
+        const RecEK<T, NS> cd = sh.get(sdn, dn);
         T jt1[NS], jt2[NS], g1, g2;
         link_flux<T, DEV, NS, h, CLEAN>(s, me, cu, K, jt1, g1);
         link_flux<T, DEV, NS, h, CLEAN>(s, cd, me, K, jt2, g2);
@@ -372,7 +251,7 @@ __device__ __forceinline__ unsigned lb_bmask_lds(const EKShared<T, NS, TXW, TYW>
         if constexpr (i > 0) {
             constexpr int cx = q19x(i), cy = q19y(i), cz = q19z(i);
             const int slot = cz > 0 ? sm : (cz < 0 ? sp : s0);
-            m |= (unsigned)sh.rec[slot][ctr - cy * SH::WX - cx].wall() << i;
+            m |= (unsigned)sh.wall(slot, ctr - cy * SH::WX - cx) << i;
         }
     });
     return m;
@@ -428,7 +307,7 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
     for (int z = zbeg; z < zend; ++z) {
         const int sm = (z + 2) % 3, s0 = z % 3, sp = (z + 1) % 3;
         // plane z is staged since the previous iteration
-        const bool wall = valid && sh.rec[s0][ctr].wall();
+        const bool wall = valid && sh.wall(s0, ctr);
         T fi[FUSE ? 19 : 1];
         if constexpr (FUSE && PREFETCH) {
             if (valid && !wall) lb_pull(s, Nbr(x, y, z, s.nx, s.ny, s.nz), fi);
@@ -455,7 +334,7 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
             for (int k = 0; k < NS; ++k) {
                 T out;
                 if (wall) out = DEV ? (T)(-s.rho_ref[k]) : (T)0;
-                else out = sh.rec[s0][ctr].r(k) + dr[k];
+                else out = sh.elem(s0, ctr, k) + dr[k];
                 st32_nt(rout + (long)k * s.N, c, out);
             }
             st32_nt(s.fext, c, fe[0]);
@@ -482,40 +361,6 @@ template <typename T, bool DEV, int NS, int TXW, int TYW, bool FUSE, bool PREFET
 __global__ __launch_bounds__(TXW* TYW) __attribute__((amdgpu_waves_per_eu(2))) void k_ek(Sim<T> s, int ZC, int gx,
                                                                                           int gy, int ntiles) {
     ek_body<T, DEV, NS, TXW, TYW, FUSE, PREFETCH>(s, blockIdx.x, blockIdx.y, gridDim.x, ZC, gx, gy, ntiles);
-}
-
-// ---------------------------------------------------------------------------
-// LB (unfused kernel)
-// ---------------------------------------------------------------------------
-// Workgroup b covers cells [256 (b mod nbp), 256 (b mod nbp) + 256) of plane
-// z = b div nbp, nbp = ceil(nx ny / 256); the in-plane division by nx is
-// exact by multiply-high (nx ny nx < 2^27).
-template <typename T, bool DEV>
-__device__ __forceinline__ void lb_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    const int nx = s.nx, ny = s.ny, P = nx * ny;
-    const int nbp = (P + BT - 1) / BT;
-    const int z = bx_ / nbp;
-    const int cp = (bx_ - z * nbp) * BT + threadIdx.x;
-    if (cp >= P) return;
-    const int y = FDiv(nx).div(cp);
-    const uint32_t c = (uint32_t)z * (uint32_t)P + (uint32_t)cp;
-    const Nbr nb(cp - y * nx, y, z, nx, ny, s.nz);
-    // all loads first (a boundary cell's pulls are wasted, but harmless),
-    // boundary fix-ups (rare) afterwards
-    T fi[19];
-    lb_pull(s, nb, fi);
-    const uint8_t fl = ld32(s.flag, c);
-    const T fx = ld32(s.fext, c), fy = ld32(s.fext + s.N, c), fz = ld32(s.fext + 2 * s.N, c);
-    if (fl & F_CUR) {
-        lb_wall(s, c);
-        return;
-    }
-    lb_collide<T, DEV>(s, c, nb, fi, lb_bmask_global(s, nb), fx, fy, fz);
-}
-
-template <typename T, bool DEV>
-__global__ __launch_bounds__(BT) void k_lb(Sim<T> s) {
-    lb_body<T, DEV>(s, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -553,8 +398,7 @@ void launch_fields(const Sim<T>& s, hipStream_t st, hipEvent_t mid) {
     constexpr bool DEV = sizeof(T) == 4;
     launch_ek<T, kFuseFields<T>>(s, st);
     if (mid) (void)hipEventRecord(mid, st);
-    if constexpr (!kFuseFields<T>)
-        hipLaunchKernelGGL((k_lb<T, DEV>), dim3((unsigned)grids_of<T>(s).n[KK_LB]), dim3(BT), 0, st, s);
+    if constexpr (!kFuseFields<T>) launch_lb(s, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -572,10 +416,6 @@ __global__ __launch_bounds__(EKTile<float>::TXW* EKTile<float>::TYW) void kb_ek(
     });
 }
 
-__global__ __launch_bounds__(BT) void kb_lb(const BatchTable* tab) {
-    batch_loop<KK_LB>(tab, [](const Sim<float>& s, int b) { lb_body<float, true>(s, b, 0, 0); });
-}
-
 void launch_batch_fields(const BatchTable* tab, int ns, hipStream_t st) {
     constexpr int NT = EKTile<float>::TXW * EKTile<float>::TYW;
     switch (ns) {
@@ -584,7 +424,7 @@ void launch_batch_fields(const BatchTable* tab, int ns, hipStream_t st) {
         case 3: hipLaunchKernelGGL(kb_ek<3>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
         default: hipLaunchKernelGGL(kb_ek<4>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
     }
-    if constexpr (!kFuseFields<float>) hipLaunchKernelGGL(kb_lb, dim3(BATCH_FIELD_BLOCKS), dim3(BT), 0, st, tab);
+    if constexpr (!kFuseFields<float>) launch_batch_lb(tab, st);
 }
 
 template void launch_fields<float>(const Sim<float>&, hipStream_t, hipEvent_t);
