@@ -44,6 +44,9 @@ __device__ __forceinline__ void st32_nt(T* __restrict__ base, uint32_t e, T v) {
 // Periodic neighbour coordinates of one cell.
 struct Nbr {
     int x, y, z, xm, xp, ym, yp, zm, zp;
+    // index of the cell and the index offsets of its periodic neighbours
+    uint32_t c;
+    int dxm, dxp, dym, dyp, dzm, dzp;
     __device__ __forceinline__ Nbr(int x_, int y_, int z_, int nx, int ny, int nz) : x(x_), y(y_), z(z_) {
         xm = x == 0 ? nx - 1 : x - 1;
         xp = x == nx - 1 ? 0 : x + 1;
@@ -51,14 +54,29 @@ struct Nbr {
         yp = y == ny - 1 ? 0 : y + 1;
         zm = z == 0 ? nz - 1 : z - 1;
         zp = z == nz - 1 ? 0 : z + 1;
+        const int P = nx * ny;
+        c = (uint32_t)x + (uint32_t)nx * ((uint32_t)y + (uint32_t)ny * (uint32_t)z);
+        dxm = xm - x;
+        dxp = xp - x;
+        dym = (ym - y) * nx;
+        dyp = (yp - y) * nx;
+        dzm = (zm - z) * P;
+        dzp = (zp - z) * P;
     }
     // source cell r - c_i of population i
     __device__ __forceinline__ int sx(int i) const { return q19x(i) > 0 ? xm : (q19x(i) < 0 ? xp : x); }
     __device__ __forceinline__ int sy(int i) const { return q19y(i) > 0 ? ym : (q19y(i) < 0 ? yp : y); }
     __device__ __forceinline__ int sz(int i) const { return q19z(i) > 0 ? zm : (q19z(i) < 0 ? zp : z); }
-    template <typename T>
-    __device__ __forceinline__ long src(const Sim<T>& s, int i) const {
-        return cidx3(s, sx(i), sy(i), sz(i));
+    // its index: c plus the offsets of the axes along which c_i is non-zero
+    __device__ __forceinline__ uint32_t src32(int i) const {
+        int d = 0;
+        if (q19x(i) > 0) d += dxm;
+        if (q19x(i) < 0) d += dxp;
+        if (q19y(i) > 0) d += dym;
+        if (q19y(i) < 0) d += dyp;
+        if (q19z(i) > 0) d += dzm;
+        if (q19z(i) < 0) d += dzp;
+        return c + (uint32_t)d;
     }
 };
 
@@ -68,7 +86,7 @@ __device__ __forceinline__ void lb_pull(const Sim<T>& s, const Nbr& nb, T (&fi)[
     const T* __restrict__ fs = s.f[s.cur];
     sfor<19>([&](auto I) {
         constexpr int i = I;
-        fi[i] = ld32(fs + (long)i * s.N, cidx32(s, nb.sx(i), nb.sy(i), nb.sz(i)));
+        fi[i] = ld32(fs + (long)i * s.N, nb.src32(i));
     });
 }
 
@@ -78,7 +96,7 @@ __device__ __forceinline__ unsigned lb_bmask_global(const Sim<T>& s, const Nbr& 
     unsigned bmask = 0;
     sfor<19>([&](auto I) {
         constexpr int i = I;
-        if constexpr (i > 0) bmask |= (unsigned)(ld32(s.flag, cidx32(s, nb.sx(i), nb.sy(i), nb.sz(i))) & F_CUR) << i;
+        if constexpr (i > 0) bmask |= (unsigned)(ld32(s.flag, nb.src32(i)) & F_CUR) << i;
     });
     return bmask;
 }
@@ -100,7 +118,7 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
                     // moving bounce-back from the boundary cell b = r - c_i
                     const int bx = nb.sx(i), by = nb.sy(i), bz = nb.sz(i);
                     double vb[3] = {0.0, 0.0, 0.0};
-                    uint16_t ow = s.owner[cidx3(s, bx, by, bz)];
+                    uint16_t ow = ld32(s.owner, nb.src32(i));
                     if (ow != NO_OWNER) {
                         const PState& q = s.parts[ow];
                         double r[3] = {min_image((double)bx + 0.5, q.x[0], (double)nx),
@@ -116,32 +134,42 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
             }
         });
     }
-    T rho = (T)0, jx = (T)0, jy = (T)0, jz = (T)0;
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        rho += fi[i];
-        if constexpr (q19x(i) != 0) jx += (T)q19x(i) * fi[i];
-        if constexpr (q19y(i) != 0) jy += (T)q19y(i) * fi[i];
-        if constexpr (q19z(i) != 0) jz += (T)q19z(i) * fi[i];
+    // Moments from the pair sums and differences of (i, ibar) (i odd, ibar = i + 1).
+    T rho = fi[0], jx = (T)0, jy = (T)0, jz = (T)0;
+    T ps[19], pd[19];
+    sfor<9>([&](auto P) {
+        constexpr int i = 2 * P + 1, o = i + 1;
+        ps[i] = fi[i] + fi[o];
+        pd[i] = fi[i] - fi[o];
+        rho += ps[i];
+        if constexpr (q19x(i) != 0) jx += (T)q19x(i) * pd[i];
+        if constexpr (q19y(i) != 0) jy += (T)q19y(i) * pd[i];
+        if constexpr (q19z(i) != 0) jz += (T)q19z(i) * pd[i];
     });
     const T ux = jx + (T)0.5 * fx, uy = jy + (T)0.5 * fy, uz = jz + (T)0.5 * fz;
     const T usq = ux * ux + uy * uy + uz * uz;
     const T uf = ux * fx + uy * fy + uz * fz;
     const T le = s.lam_e, lo = s.lam_o;
     const T g2 = (T)2 + le;
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        constexpr int o = q19opp(i);
+    const T uf3 = uf / (T)3;
+    {  // rest population: even part only
+        const T w = (T)q19w(0);
+        const T feq_e = w * (rho - (T)1.5 * usq);
+        st32_nt(fd, c, fi[0] + le * (fi[0] - feq_e) + (T)4.5 * w * g2 * (-uf3));
+    }
+    // TRT per pair: the even part (symmetric relaxation and the even forcing
+    // term) is shared by i and ibar, the odd part changes sign.
+    sfor<9>([&](auto P) {
+        constexpr int i = 2 * P + 1, o = i + 1;
         const T w = (T)q19w(i);
         const T cu = (T)q19x(i) * ux + (T)q19y(i) * uy + (T)q19z(i) * uz;
         const T cj = (T)q19x(i) * jx + (T)q19y(i) * jy + (T)q19z(i) * jz;
         const T cf = (T)q19x(i) * fx + (T)q19y(i) * fy + (T)q19z(i) * fz;
         const T feq_e = w * (rho + (T)4.5 * cu * cu - (T)1.5 * usq);
-        const T feq_o = w * (T)3 * cj;
-        const T fp = (T)0.5 * (fi[i] + fi[o]);
-        const T fm = (T)0.5 * (fi[i] - fi[o]);
-        const T delta = (T)3 * w * (cf + (T)1.5 * (g2 * cu * cf - g2 * uf / (T)3));
-        st32_nt(fd + (long)i * s.N, c, fi[i] + le * (fp - feq_e) + lo * (fm - feq_o) + delta);
+        const T ev = le * ((T)0.5 * ps[i] - feq_e) + (T)4.5 * w * g2 * (cu * cf - uf3);
+        const T od = lo * ((T)0.5 * pd[i] - (T)3 * w * cj) + (T)3 * w * cf;
+        st32_nt(fd + (long)i * s.N, c, fi[i] + ev + od);
+        st32_nt(fd + (long)o * s.N, c, fi[o] + ev - od);
     });
     st32_nt(uo, c, ux);
     st32_nt(uo + s.N, c, uy);
