@@ -71,6 +71,27 @@ __device__ __forceinline__ void dft_small(cpx<T> (&v)[R]) {
         v[2] = csub<T>(s02, s13);
         v[1] = cadd<T>(d02, rot);
         v[3] = csub<T>(d02, rot);
+    } else if constexpr (R == 8) {
+        // even/odd split: E = DFT4(v0, v2, v4, v6), O = DFT4(v1, v3, v5, v7),
+        // X[k] = E[k] + W8^k O[k], X[k+4] = E[k] - W8^k O[k]
+        cpx<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<T, 4, INV>(e);
+        dft_small<T, 4, INV>(o);
+        const T h = (T)0.70710678118654752440;
+        // W8^1 = (1 -+ i) h, W8^2 = -+ i, W8^3 = (-1 -+ i) h (upper sign forward)
+        const cpx<T> t1 = INV ? mk<T>(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
+                              : mk<T>(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+        const cpx<T> t2 = INV ? mk<T>(-o[2].y, o[2].x) : mk<T>(o[2].y, -o[2].x);
+        const cpx<T> t3 = INV ? mk<T>(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
+                              : mk<T>(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+        v[0] = cadd<T>(e[0], o[0]);
+        v[4] = csub<T>(e[0], o[0]);
+        v[1] = cadd<T>(e[1], t1);
+        v[5] = csub<T>(e[1], t1);
+        v[2] = cadd<T>(e[2], t2);
+        v[6] = csub<T>(e[2], t2);
+        v[3] = cadd<T>(e[3], t3);
+        v[7] = csub<T>(e[3], t3);
     } else {  // R == 3
         const T c3 = (T)-0.5;
         const T s3 = INV ? (T)0.86602540378443864676 : (T)-0.86602540378443864676;
@@ -134,6 +155,61 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
     __syncthreads();
 }
 
+// The same stage with the length, radix and stride known at compile time
+// (power-of-two lengths): every index is a shift or a mask.
+template <typename T, int N, int R, int NS, bool INV>
+__device__ __forceinline__ void stage_c(cpx<T>* a, int P, int ld, const cpx<T>* __restrict__ tw) {
+    constexpr int NB = (FE + R - 1) / R;
+    constexpr int nR = N / R, span = N / (NS * R);
+    const int nb = P * nR;
+    cpx<T> v[NB][R];
+    int dst[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int b = threadIdx.x + q * FT;
+        dst[q] = -1;
+        if (b < nb) {
+            const int pen = b / nR, j = b % nR;
+            const int jq = j / NS, k = j % NS;
+            const cpx<T>* src = a + pen * ld;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                cpx<T> x = src[j + r * nR];
+                if (NS > 1 && r > 0 && k > 0) {
+                    cpx<T> w = tw[k * r * span];
+                    if (INV) w.y = -w.y;
+                    x = cmul<T>(x, w);
+                }
+                v[q][r] = x;
+            }
+            dst[q] = pen * ld + jq * NS * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if (dst[q] >= 0) {
+            dft_small<T, R, INV>(v[q]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[dst[q] + r * NS] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Radix plan of a power-of-two length: 8 while at least 8 remains, then 4 or 2.
+template <int M>
+constexpr int radix_of() { return M % 8 == 0 ? 8 : (M % 4 == 0 ? 4 : 2); }
+
+template <typename T, int N, bool INV, int NS = 1>
+__device__ __forceinline__ void fft_lds_c(cpx<T>* a, int P, int ld, const cpx<T>* __restrict__ tw) {
+    if constexpr (NS < N) {
+        constexpr int R = radix_of<N / NS>();
+        stage_c<T, N, R, NS, INV>(a, P, ld, tw);
+        fft_lds_c<T, N, INV, NS * R>(a, P, ld, tw);
+    }
+}
+
 // In-place FFT of P pencils (P * n <= FT * FE) in LDS; all threads participate.
 // Forward uses e^{-2 pi i m / n} from tw; INV the conjugate.
 // Radices in the order 4, 4, ..., (2), 3, 3, ...: the greedy choice below
@@ -168,6 +244,20 @@ __device__ __forceinline__ const cpx<T>* stage_twiddles(cpx<T>* a, int data_elem
     return t;
 }
 
+// Compile-time plans for the power-of-two lengths from 32 to 512, the
+// runtime plan otherwise.
+template <typename T, bool INV>
+__device__ __forceinline__ void fft_any(cpx<T>* a, int n, int P, int ld, const cpx<T>* __restrict__ tw) {
+    switch (n) {
+        case 32: fft_lds_c<T, 32, INV>(a, P, ld, tw); break;
+        case 64: fft_lds_c<T, 64, INV>(a, P, ld, tw); break;
+        case 128: fft_lds_c<T, 128, INV>(a, P, ld, tw); break;
+        case 256: fft_lds_c<T, 256, INV>(a, P, ld, tw); break;
+        case 512: fft_lds_c<T, 512, INV>(a, P, ld, tw); break;
+        default: fft_lds<T, INV>(a, n, P, ld, tw); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Pass X (forward): charge assembly + two-for-one real FFT along x.
 // Work item: a pair of rows (y, y+1) at one z.  P pairs per workgroup.
@@ -200,7 +290,7 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
         a[pen * ld + x] = v;
     }
     __syncthreads();
-    fft_lds<T, false>(a, n, P, ld, tw);
+    fft_any<T, false>(a, n, P, ld, tw);
     const cpx<T>* r = a;
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
     const int nh = s.nxh;
@@ -255,7 +345,7 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
         a[pen * ld + k] = v;
     }
     __syncthreads();
-    fft_lds<T, true>(a, n, P, ld, tw);
+    fft_any<T, true>(a, n, P, ld, tw);
     for (int t = threadIdx.x; t < P * n; t += FT) {
         int pen = dn.div(t), x = t - pen * n;
         int pr = pair0 + pen;
@@ -294,7 +384,7 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int by_, in
         a[i * ld + y] = S[(long)y * nh + kx0 + i];
     }
     __syncthreads();
-    fft_lds<T, INV>(a, n, TC, ld, tw);
+    fft_any<T, INV>(a, n, TC, ld, tw);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
         int y = dtc.div(t), i = t - y * TC;
         S[(long)y * nh + kx0 + i] = a[i * ld + y];
@@ -327,7 +417,7 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
         a[i * ld + z] = S[z * zstride + (long)ky * nh + kx0 + i];
     }
     __syncthreads();
-    fft_lds<T, false>(a, n, TC, ld, tw);
+    fft_any<T, false>(a, n, TC, ld, tw);
     const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
         int i = dn.div(t), kz = t - i * n;
@@ -338,7 +428,7 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
         a[i * ld + kz] = mk<T>(v.x * g, v.y * g);
     }
     __syncthreads();
-    fft_lds<T, true>(a, n, TC, ld, tw);
+    fft_any<T, true>(a, n, TC, ld, tw);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
         int z = dtc.div(t), i = t - z * TC;
         S[z * zstride + (long)ky * nh + kx0 + i] = a[i * ld + z];
