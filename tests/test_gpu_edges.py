@@ -1,0 +1,110 @@
+"""GPU parity on edge cases of the lattice and the method, through the C ABI.
+
+- The largest allowed edge (512) along each axis in turn, with the smallest
+  (8) and a 3-factor edge (12) on the others: every FFT plan length at its
+  extreme, the x pass with four pencil pairs per workgroup, y/z tiles of a
+  single or few kx columns.
+- 3-factor edges 384 and 192 (runtime radix plans with radix-3 stages).
+- No particles at all (pure electrokinetic flow in a field).
+- A neutral sphere at rest in no field: the equilibrium must stay put.
+Each case is compared against the oracle after a few steps; flags, owners and
+Psi must agree exactly."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1607_04572_amd import workloads as W
+from parity_util import compare, make_gpu, make_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def ok64(e):
+    assert e["flag_mismatch"] == 0 and e["owner_mismatch"] == 0 and e["psi"] == 0.0
+    for k in ("density", "phi", "velocity", "populations", "force", "rhob"):
+        assert e[k] < 1e-9, k
+
+
+def ok32(e, dens=1e-5):
+    assert e["flag_mismatch"] == 0 and e["owner_mismatch"] == 0 and e["psi"] == 0.0
+    assert e["density"] < dens
+    for k in ("phi", "velocity", "populations", "force"):
+        assert e[k] < 1e-4, k
+
+
+def ok32_strong_field(e):
+    # A sphere of valency 15 in a box 8 cells thick raises the potential to
+    # |phi| ~ 50 (oracle); its FP32 rounding, ~3e-7 relative after the
+    # transforms, i.e. ~1.5e-5 absolute, enters every migration flux as
+    # D/(A0|s|) z/2 (rho_a + rho_b) d(phi_a - phi_b) ~ 2e-8 per link and step:
+    # over up to 18 links and 4 steps at most ~2e-6, 2e-4 of the mean 0.01.
+    # Observed: 1.7e-5.
+    ok32(e, dens=1e-4)
+
+
+def run_case(w, steps, ok):
+    say(f"case {w.name} shape {w.shape} {w.precision} spheres {len(w.spheres)}")
+    g = make_gpu(w)
+    o = make_oracle(w)
+    g.prepare()
+    g.step(steps)
+    o.run(steps)
+    e = compare(w, g, o, f"{w.name} step {steps}")
+    ok(e)
+    g.close()
+    return e
+
+
+def sphere_case(name, shape, precision, R=2.5, E=(0.02, 0.01, 0.0), Z=15.0):
+    c = tuple(0.5 * n + 0.3 for n in shape)
+    return W.Workload(name=name, shape=shape, precision=precision, species=W.salt(0.3, 0.01), lambda_B=0.7,
+                      E=E, steps=5, spheres=[W.Sphere(x=c, R=R, Z=Z, M=2 * W.sphere_volume(R), v=(0.004, 0.0, 0.0),
+                                                      mode=1)])
+
+
+@pytest.mark.parametrize("shape", [(512, 8, 12), (12, 512, 8), (8, 12, 512)])
+def test_max_edge_each_axis_fp64(shape):
+    run_case(sphere_case("max_edge", shape, "fp64"), 4, ok64)
+
+
+@pytest.mark.parametrize("shape", [(512, 8, 12), (8, 12, 512)])
+def test_max_edge_fp32(shape):
+    run_case(sphere_case("max_edge32", shape, "fp32"), 4, ok32_strong_field)
+
+
+@pytest.mark.parametrize("shape", [(384, 12, 8), (8, 192, 24)])
+def test_three_factor_edges(shape):
+    run_case(sphere_case("three_factor", shape, "fp64"), 4, ok64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_no_particles(precision):
+    w = W.Workload(name="no_particles", shape=(24, 16, 12), precision=precision, species=W.salt(0.3, 0.01),
+                   lambda_B=0.7, E=(0.02, -0.01, 0.005), steps=10, spheres=[])
+    run_case(w, 10, ok64 if precision == "fp64" else ok32)
+
+
+def test_neutral_sphere_at_rest_stays_at_equilibrium():
+    """Uniform salt (no noise), a neutral sphere held at rest, no field: the
+    initial state (densities (1 - Psi) c in partial-volume cells) is stationary,
+    so the fluid stays at rest and the densities do not move.  Both sides are
+    checked against that state in absolute terms (relative errors of a field
+    that is zero up to rounding mean nothing)."""
+    w = sphere_case("rest", (16, 16, 16), "fp64", R=3.0, E=(0.0, 0.0, 0.0), Z=0.0)
+    w = w.replace(noise=0.0, spheres=[dataclasses.replace(s, v=(0.0, 0.0, 0.0)) for s in w.spheres])
+    say(f"case {w.name}")
+    g = make_gpu(w)
+    o = make_oracle(w)
+    g.prepare()
+    g.step(20)
+    o.run(20)
+    e = compare(w, g, o, "rest step 20")
+    assert e["flag_mismatch"] == 0 and e["owner_mismatch"] == 0 and e["psi"] == 0.0
+    psi = g.field("psi")
+    fluid = g.field("flag") == 0
+    for u, rho in ((g.field("velocity"), g.field("density").reshape(2, -1)), (o.u, o.density())):
+        assert np.max(np.abs(u)) < 1e-12
+        for k in range(2):
+            assert np.max(np.abs(rho[k][fluid] - 0.01 * (1.0 - psi[fluid]))) < 1e-12
+    g.close()
