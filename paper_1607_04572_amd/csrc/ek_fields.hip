@@ -47,11 +47,17 @@ struct alignas(16) RecEK {
 };
 
 // Per-species constants of the link flux, hoisted out of the cell loop.
+// Dc[k][0/1] = D_k / (A0 |s|) for |s| = 1 and sqrt 2 (the link-length
+// factor of the diffusive/migrative flux).
 template <typename T, int NS>
 struct EKConst {
     T D[NS], hz[NS], ref[NS], ref2hz[NS];
-    T Es[13], coef[13];
+    T Es[13], Dc[NS][2];
 };
+
+// 1 / (A0 |s|) of half-direction h (A0 = 1 + 2 sqrt 2).
+template <int H>
+constexpr double link_coef() { return 1.0 / ((1.0 + 2.0 * 1.4142135623730950488) * hlen(H)); }
 
 // Fraction of a cell moving with velocity u that lands in the neighbour at
 // offset s along one axis: |u| if s has the sign of u, 1 - |u| if s = 0, else 0.
@@ -74,10 +80,33 @@ __device__ __forceinline__ T vof_frac(T ux, T uy, T uz) {
 // formula then reduces exactly (multiplications by 1 and additions of 0 are
 // exact) to the clean one, so both evaluations of a link give the same bits
 // whichever path they take.
+// The advective fractions of one cell for every direction, from its nine
+// axis factors and their x-y pair products: g(s; u) = (f_x f_y) f_z, the same
+// operations in the same order as vof_frac, so both ends of a link still
+// evaluate it bit for bit alike.
+template <typename T>
+struct VofCell {
+    T fz[3], pxy[3][3];
+    __device__ __forceinline__ VofCell(T ux, T uy, T uz) {
+        const T fx[3] = {vof_axis<T, -1>(ux), vof_axis<T, 0>(ux), vof_axis<T, 1>(ux)};
+        const T fy[3] = {vof_axis<T, -1>(uy), vof_axis<T, 0>(uy), vof_axis<T, 1>(uy)};
+        fz[0] = vof_axis<T, -1>(uz);
+        fz[1] = vof_axis<T, 0>(uz);
+        fz[2] = vof_axis<T, 1>(uz);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) pxy[i][j] = fx[i] * fy[j];
+    }
+    template <int SX, int SY, int SZ>
+    __device__ __forceinline__ T frac() const { return pxy[SX + 1][SY + 1] * fz[SZ + 1]; }
+};
+
+// ga = g(s; u_a), gb = g(-s; u_b) are passed in (one end's fractions come
+// from its VofCell).
 template <typename T, bool DEV, int NS, int H, bool CLEAN>
 __device__ __forceinline__ void link_flux(const Sim<T>& s, const RecEK<T, NS>& a, const RecEK<T, NS>& b,
-                                          const EKConst<T, NS>& K, T (&jt)[NS], T& gsum) {
-    constexpr int SX = hx(H), SY = hy(H), SZ = hz(H);
+                                          const EKConst<T, NS>& K, const T ga, const T gb, T (&jt)[NS], T& gsum) {
     gsum = (T)0;
     if constexpr (!CLEAN) {
         if (a.wall() || b.wall()) {
@@ -87,8 +116,6 @@ __device__ __forceinline__ void link_flux(const Sim<T>& s, const RecEK<T, NS>& a
         }
     }
     const T dphi = (a.phi() - b.phi()) + K.Es[H];
-    const T ga = vof_frac<T, SX, SY, SZ>(a.ux(), a.uy(), a.uz());
-    const T gb = vof_frac<T, -SX, -SY, -SZ>(b.ux(), b.uy(), b.uz());
     T pa = (T)0, pb = (T)0, oa = (T)1, ob = (T)1;
     if constexpr (!CLEAN) {
         pa = s.pv ? a.psi() : (T)0;
@@ -117,12 +144,15 @@ __device__ __forceinline__ void link_flux(const Sim<T>& s, const RecEK<T, NS>& a
             else mig += K.hz[k] * (K.ref[k] * (oa + ob));
             adv += K.ref[k] * dg;
         }
-        T g = (T)0;
         if constexpr (H < 9) {
-            g = (A + mig * dphi) * K.coef[H];
+            // g = (A + mig dphi): the flux over D/(A0|s|); gsum collects it for
+            // the friction, which the caller scales by 1/(A0|s|)
+            const T g = A + mig * dphi;
             gsum += g;
+            jt[k] = K.Dc[k][hlen(H) > 1.0 ? 1 : 0] * g + adv;
+        } else {
+            jt[k] = adv;
         }
-        jt[k] = K.D[k] * g + adv;
     }
 }
 
@@ -214,6 +244,7 @@ __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T
                                                int sp, int ctr, const EKConst<T, NS>& K, T (&dr)[NS], T (&fe)[3]) {
     using SH = EKShared<T, NS, TXW, TYW>;
     const RecEK<T, NS> me = sh.get(s0, ctr);
+    const VofCell<T> mv(me.ux(), me.uy(), me.uz());
     sfor<13>([&](auto HH) {
         constexpr int h = HH;
         constexpr int ox = hx(h), oy = hy(h), oz = hz(h);
@@ -223,13 +254,15 @@ __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T
         const RecEK<T, NS> cu = sh.get(sup, up);
         const RecEK<T, NS> cd = sh.get(sdn, dn);
         T jt1[NS], jt2[NS], g1, g2;
-        link_flux<T, DEV, NS, h, CLEAN>(s, me, cu, K, jt1, g1);
-        link_flux<T, DEV, NS, h, CLEAN>(s, cd, me, K, jt2, g2);
+        link_flux<T, DEV, NS, h, CLEAN>(s, me, cu, K, mv.template frac<ox, oy, oz>(),
+                                        vof_frac<T, -ox, -oy, -oz>(cu.ux(), cu.uy(), cu.uz()), jt1, g1);
+        link_flux<T, DEV, NS, h, CLEAN>(s, cd, me, K, vof_frac<T, ox, oy, oz>(cd.ux(), cd.uy(), cd.uz()),
+                                        mv.template frac<-ox, -oy, -oz>(), jt2, g2);
 #pragma unroll
         for (int k = 0; k < NS; ++k) dr[k] += jt2[k] - jt1[k];
         if constexpr (h < 9) {
             // each link's friction is shared by its two cells (scaled by kT/2 below)
-            const T g = g1 + g2;
+            const T g = (g1 + g2) * (T)link_coef<h>();
             if constexpr (ox > 0) fe[0] += g;
             if constexpr (ox < 0) fe[0] -= g;
             if constexpr (oy > 0) fe[1] += g;
@@ -280,10 +313,11 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
     sfor<13>([&](auto HH) {
         constexpr int h = HH;
         K.Es[h] = (T)(s.E[0] * hx(h) + s.E[1] * hy(h) + s.E[2] * hz(h));
-        K.coef[h] = (T)(1.0 / ((1.0 + 2.0 * 1.4142135623730950488) * hlen(h)));
     });
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
+        K.Dc[k][0] = (T)(s.D[k] * link_coef<0>());
+        K.Dc[k][1] = (T)(s.D[k] * link_coef<3>());
         K.D[k] = (T)s.D[k];
         K.hz[k] = (T)(0.5 * s.z[k]);
         K.ref[k] = (T)s.rho_ref[k];
