@@ -484,8 +484,9 @@ __device__ __forceinline__ double rho_abs(const Sim<T>& s, const T* r, int k, lo
 // applied at the cell centre); a vacated cell is filled with the equilibrium
 // at the surface velocity and the mean density of its stable-fluid D3Q19
 // neighbours (1 if none), and its momentum is taken from the particle.
-// Also counts the particle's boundary cells (n_b) and collects the solute of
-// covered cells that have no stable-fluid neighbour at all (global pool).
+// Also counts the particle's boundary cells (n_b), collects the solute of
+// covered cells that have no stable-fluid neighbour at all (global pool), and
+// performs the solute expel for the stable cells of the box (expel_cell).
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_, int gx_) {
@@ -507,6 +508,7 @@ __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_,
         uint8_t fl = s.flag[c];
         if ((fl & F_CUR) && s.owner[c] == p) acc[6 + MAXS + 3] += 1.0;  // n_b
         if ((fl & (F_CUR | F_PREV)) && !(fl & F_WALL) && box_owner_is(s, L, p, x, y, z)) acc[6 + MAXS + 4] += 1.0;
+        if (stable(fl) && box_owner_is(s, L, p, x, y, z)) expel_cell(s, s.rho[s.cur], x, y, z, c);
         if (covered(fl) && s.owner[c] == p) {
             double pf[3] = {0.0, 0.0, 0.0};
             sfor<19>([&](auto I) {
@@ -593,99 +595,82 @@ __global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
     boundary_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
-// Chunk partials of k_boundary -> particle record, summed in chunk order.
-template <typename T>
-__device__ __forceinline__ void boundary_reduce_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    constexpr int NV = 6 + MAXS + 5;
-    const int p = bx_, k = threadIdx.x;
-    // all chunk partials are fetched at once, then summed in chunk order
-    __shared__ double buf[MAX_CHUNKS][NV];
-    for (int e = threadIdx.x; e < s.nchunk * NV; e += blockDim.x)
-        buf[e / NV][e % NV] = partial_rec(s, PART_BOUNDARY, p, e / NV)[e % NV];
-    __syncthreads();
-    if (k >= NV) return;
-    double v = 0.0;
-    for (int c = 0; c < s.nchunk; ++c) v += buf[c][k];
-    PState& me = s.parts[p];
-    if (k < 3) me.Fc[k] = v;
-    else if (k < 6) me.Tc[k - 3] = v;
-    else if (k < 6 + MAXS) me.pool[k - 6] = v;
-    else if (k == 6 + MAXS) me.ncov = (int)v;
-    else if (k == 6 + MAXS + 1) me.nvac = (int)v;
-    else if (k == 6 + MAXS + 2) me.npool = (int)v;
-    else if (k == 6 + MAXS + 3) me.nb = (int)v;
-    else me.nflag = (int)v;
-}
-
-template <typename T>
-__global__ void k_boundary_reduce(Sim<T> s) {
-    boundary_reduce_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
-}
-
 // ---------------------------------------------------------------------------
-// Solute expel (Sec. III.D.1), gather form in FP64: every stable-fluid cell
+// Solute expel (Sec. III.D.1), gather form in FP64: every stable-fluid cell n
 // collects, from each covered neighbour c, rho(c)/n19(c) if it is one of c's
 // n19 stable D3Q19 neighbours; if c has no such neighbour, rho(c)/n27(c) from
-// the D3Q27 neighbourhood.  Covered cells are emptied by k_boundary_post.
+// the D3Q27 neighbourhood.  Covered cells are emptied afterwards (boundary
+// post).  Runs inside the boundary kernel: it reads flags and the densities of
+// covered cells and writes those of stable cells, none of which the boundary
+// work there writes or reads.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void expel_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    const int p = by_;
-    const PLocal me(s.parts[p]);
-    const BoxWalk bw(me);
-    __shared__ NbrList L;
-    build_nbrs(s, me, L);
-    T* rho = s.rho[s.cur];
-    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += gx_ * PT) {
-        int x, y, z;
-        bw.cell(s, t, x, y, z);
-        long n = cidx(s, x, y, z);
-        if (!stable(s.flag[n])) continue;
-        if (!box_owner_is(s, L, p, x, y, z)) continue;
-        double gain[MAXS] = {0.0, 0.0, 0.0, 0.0};
-        bool any = false;
-        for (int a = -1; a <= 1; ++a)
-            for (int b = -1; b <= 1; ++b)
-                for (int e = -1; e <= 1; ++e) {
-                    if (!(a | b | e)) continue;
-                    long c = cidx(s, x + a, y + b, z + e);
-                    if (!covered(s.flag[c])) continue;
-                    int cx = x + a, cy = y + b, cz = z + e;
-                    int n19 = 0, n27 = 0;
-                    for (int a2 = -1; a2 <= 1; ++a2)
-                        for (int b2 = -1; b2 <= 1; ++b2)
-                            for (int e2 = -1; e2 <= 1; ++e2) {
-                                if (!(a2 | b2 | e2)) continue;
-                                if (!stable(s.flag[cidx(s, cx + a2, cy + b2, cz + e2)])) continue;
-                                n27++;
-                                if (abs(a2) + abs(b2) + abs(e2) <= 2) n19++;
-                            }
-                    bool is19 = abs(a) + abs(b) + abs(e) <= 2;
-                    int div = 0;
-                    if (n19 > 0) div = is19 ? n19 : 0;
-                    else if (n27 > 0) div = n27;
-                    if (div == 0) continue;
-                    any = true;
-                    for (int k = 0; k < s.ns; ++k) gain[k] += rho_abs(s, rho, k, c) / div;
-                }
-        if (!any) continue;
-        for (int k = 0; k < s.ns; ++k) {
-            double v = rho_abs(s, rho, k, n) + gain[k];
-            rho[(long)k * s.N + n] = (T)(sizeof(T) == 4 ? v - s.rho_ref[k] : v);
-        }
+__device__ __forceinline__ void expel_cell(const Sim<T>& s, T* rho, int x, int y, int z, long n) {
+    double gain[MAXS] = {0.0, 0.0, 0.0, 0.0};
+    bool any = false;
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+            for (int e = -1; e <= 1; ++e) {
+                if (!(a | b | e)) continue;
+                long c = cidx(s, x + a, y + b, z + e);
+                if (!covered(s.flag[c])) continue;
+                int cx = x + a, cy = y + b, cz = z + e;
+                int n19 = 0, n27 = 0;
+                for (int a2 = -1; a2 <= 1; ++a2)
+                    for (int b2 = -1; b2 <= 1; ++b2)
+                        for (int e2 = -1; e2 <= 1; ++e2) {
+                            if (!(a2 | b2 | e2)) continue;
+                            if (!stable(s.flag[cidx(s, cx + a2, cy + b2, cz + e2)])) continue;
+                            n27++;
+                            if (abs(a2) + abs(b2) + abs(e2) <= 2) n19++;
+                        }
+                bool is19 = abs(a) + abs(b) + abs(e) <= 2;
+                int div = 0;
+                if (n19 > 0) div = is19 ? n19 : 0;
+                else if (n27 > 0) div = n27;
+                if (div == 0) continue;
+                any = true;
+                for (int k = 0; k < s.ns; ++k) gain[k] += rho_abs(s, rho, k, c) / div;
+            }
+    if (!any) return;
+    for (int k = 0; k < s.ns; ++k) {
+        double v = rho_abs(s, rho, k, n) + gain[k];
+        rho[(long)k * s.N + n] = (T)(sizeof(T) == 4 ? v - s.rho_ref[k] : v);
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(PT) void k_expel(Sim<T> s) {
-    expel_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
-}
-
-// Covered cells lose their solute; in the uniform charge mode each owned cell
-// receives Z / n_b of its particle's charge.
+// Chunk partials of the boundary kernel -> particle record (by the first
+// workgroup of each particle), summed in chunk order.  Then covered cells lose
+// their solute and, in the uniform charge mode, each owned cell receives
+// Z / n_b of its particle's charge (every workgroup sums n_b itself).
 template <typename T>
 __device__ __forceinline__ void boundary_post_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    constexpr int NV = 6 + MAXS + 5;
     const int p = by_;
+    __shared__ double buf[MAX_CHUNKS][NV];
+    __shared__ int nb_sh;
+    for (int e = threadIdx.x; e < s.nchunk * NV; e += blockDim.x)
+        buf[e / NV][e % NV] = partial_rec(s, PART_BOUNDARY, p, e / NV)[e % NV];
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k < NV && (bx_ == 0 || k == 6 + MAXS + 3)) {
+        double v = 0.0;
+        for (int c = 0; c < s.nchunk; ++c) v += buf[c][k];
+        if (k == 6 + MAXS + 3) nb_sh = (int)v;
+        if (bx_ == 0) {
+            PState& q = s.parts[p];
+            if (k < 3) q.Fc[k] = v;
+            else if (k < 6) q.Tc[k - 3] = v;
+            else if (k < 6 + MAXS) q.pool[k - 6] = v;
+            else if (k == 6 + MAXS) q.ncov = (int)v;
+            else if (k == 6 + MAXS + 1) q.nvac = (int)v;
+            else if (k == 6 + MAXS + 2) q.npool = (int)v;
+            else if (k == 6 + MAXS + 3) q.nb = (int)v;
+            else q.nflag = (int)v;
+        }
+    }
+    __syncthreads();
+    const int nb = nb_sh;
     const PLocal me(s.parts[p]);
     const BoxWalk bw(me);
     T* rho = s.rho[s.cur];
@@ -696,9 +681,9 @@ __device__ __forceinline__ void boundary_post_body(const Sim<T>& s, int bx_, int
         uint8_t fl = s.flag[c];
         if (!(fl & F_CUR) || s.owner[c] != p) continue;
         if (covered(fl))
-            for (int k = 0; k < s.ns; ++k) rho[(long)k * s.N + c] = (T)(sizeof(T) == 4 ? -s.rho_ref[k] : 0.0);
-        if (s.charge_mode == EK_CHARGE_UNIFORM && me.nb > 0) {
-            double qb = (s.wall_charge ? s.wall_charge[c] : 0.0) + me.Z / (double)me.nb;
+            for (int k2 = 0; k2 < s.ns; ++k2) rho[(long)k2 * s.N + c] = (T)(sizeof(T) == 4 ? -s.rho_ref[k2] : 0.0);
+        if (s.charge_mode == EK_CHARGE_UNIFORM && nb > 0) {
+            double qb = (s.wall_charge ? s.wall_charge[c] : 0.0) + me.Z / (double)nb;
             s.rhob[c] = (T)qb;
         }
     }
@@ -1048,8 +1033,6 @@ template <typename T>
 void launch_boundary(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
     hipLaunchKernelGGL(k_boundary<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
-    hipLaunchKernelGGL(k_boundary_reduce<T>, dim3(s.np), dim3(64), 0, st, s);
-    hipLaunchKernelGGL(k_expel<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
     hipLaunchKernelGGL(k_boundary_post<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
     hipLaunchKernelGGL(k_pool<T>, dim3(POOL_BLOCKS), dim3(PT), 0, st, s);
 }
@@ -1103,14 +1086,6 @@ __global__ __launch_bounds__(PT) void kb_boundary(const BatchTable* tab) {
         boundary_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
-__global__ void kb_boundary_reduce(const BatchTable* tab) {
-    batch_loop<KK_PRED>(tab, [](const Sim<float>& s, int b) { boundary_reduce_body<float>(s, b, 0, 0); });
-}
-__global__ __launch_bounds__(PT) void kb_expel(const BatchTable* tab) {
-    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
-        expel_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
-    });
-}
 __global__ __launch_bounds__(PT) void kb_boundary_post(const BatchTable* tab) {
     batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
         boundary_post_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
@@ -1147,8 +1122,6 @@ void launch_batch_particles_pre(const BatchTable* tab, hipStream_t st) {
     hipLaunchKernelGGL(kb_move, dim3(BATCH_SMALL_BLOCKS), dim3(64), 0, st, tab);
     hipLaunchKernelGGL(kb_geometry, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
     hipLaunchKernelGGL(kb_boundary, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
-    hipLaunchKernelGGL(kb_boundary_reduce, dim3(BATCH_SMALL_BLOCKS), dim3(64), 0, st, tab);
-    hipLaunchKernelGGL(kb_expel, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
     hipLaunchKernelGGL(kb_boundary_post, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
     hipLaunchKernelGGL(kb_pool, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
     hipLaunchKernelGGL(kb_refill_vacated, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
