@@ -348,24 +348,31 @@ int run_steps(ek_ctx* c, Sim<T>& s, int n) {
     return EK_OK;
 }
 
-template <typename T>
-int prepare(ek_ctx* c, Sim<T>& s) {
-    hipStream_t st = c->stream;
-    int np = (int)c->parts.size();
+// Particle count and the workgroups per particle box of the box kernels: the
+// box extent for a displacement below one cell per step (larger displacements
+// only make their grid-stride loops take more turns).
+void set_box_chunks(ek_ctx* c) {
     int box_max = 0;
-    int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+    const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
     for (const PState& q : c->parts) {
         int b = 1;
         for (int d = 0; d < 3; ++d) {
-            int e = (int)std::ceil(2.0 * q.R) + 2 * BOX_MARGIN + 4;
+            int e = (int)std::ceil(2.0 * q.R) + 2 * BOX_MARGIN + 2;
             b *= e < n[d] ? e : n[d];
         }
         box_max = b > box_max ? b : box_max;
     }
-    c->sf.np = c->sd.np = np;
+    c->sf.np = c->sd.np = (int)c->parts.size();
     c->sf.box_max = c->sd.box_max = box_max;
     int nch = (box_max + 255) / 256;
     c->sf.nchunk = c->sd.nchunk = nch < 1 ? 1 : (nch > MAX_CHUNKS ? MAX_CHUNKS : nch);
+}
+
+template <typename T>
+int prepare(ek_ctx* c, Sim<T>& s) {
+    hipStream_t st = c->stream;
+    int np = (int)c->parts.size();
+    set_box_chunks(c);
     if (np > 0)
         HIPCHK(c, hipMemcpyAsync(s.parts, c->parts.data(), np * sizeof(PState), hipMemcpyHostToDevice, st));
     Sim<T> t = s;
@@ -844,21 +851,7 @@ int ek_set_state(ek_ctx* c, const void* host, size_t bytes) {
     c->step = h.step;
     c->set_cur(h.cur);
     if (h.prepared && !c->prepared) {
-        int np = (int)c->parts.size();
-        int box_max = 0;
-        int n[3] = {c->p.nx, c->p.ny, c->p.nz};
-        for (const PState& q : c->parts) {
-            int b = 1;
-            for (int d = 0; d < 3; ++d) {
-                int e = (int)std::ceil(2.0 * q.R) + 2 * BOX_MARGIN + 4;
-                b *= e < n[d] ? e : n[d];
-            }
-            box_max = b > box_max ? b : box_max;
-        }
-        c->sf.np = c->sd.np = np;
-        c->sf.box_max = c->sd.box_max = box_max;
-        int nch = (box_max + 255) / 256;
-        c->sf.nchunk = c->sd.nchunk = nch < 1 ? 1 : (nch > MAX_CHUNKS ? MAX_CHUNKS : nch);
+        set_box_chunks(c);
         c->prepared = true;
     }
     return EK_OK;
