@@ -364,7 +364,8 @@ void set_box_chunks(ek_ctx* c) {
     }
     c->sf.np = c->sd.np = (int)c->parts.size();
     c->sf.box_max = c->sd.box_max = box_max;
-    int nch = (box_max + 255) / 256;
+    const int per = 256 * BOX_CELLS_PER_THREAD;
+    int nch = (box_max + per - 1) / per;
     c->sf.nchunk = c->sd.nchunk = nch < 1 ? 1 : (nch > MAX_CHUNKS ? MAX_CHUNKS : nch);
 }
 

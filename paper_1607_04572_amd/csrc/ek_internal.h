@@ -28,6 +28,7 @@ constexpr int MAX_FFT = 512;
 constexpr int NDIAG = MAXS + 7;       // species totals, rho_b, fluid mass, momentum(3), boundary cells, max|u|
 constexpr int DIAG_BLOCKS = 1024;
 constexpr int MAX_CHUNKS = 32;        // workgroups per particle box
+constexpr int BOX_CELLS_PER_THREAD = 2;  // box cells per thread of a box kernel (target)
 constexpr int PSTRIDE = 16;           // doubles per partial-sum record
 enum { PART_BOUNDARY = 0, PART_HYDRO = 1, PART_EL = 2, PART_KINDS = 3 };
 
