@@ -76,14 +76,23 @@ def saturated_capacity(requests: list, arena_bytes: int = 24 << 30, chunk: int =
 
 
 def serve_benchmark(n_requests: int = 200, seed: int = 1611, load: float = 0.8, n_calibrate: int = 40,
-                    steps: int = 1000, arena_bytes: int = 24 << 30) -> dict:
+                    steps: int = 1000, arena_bytes: int = 24 << 30, extra_loads: tuple = ()) -> dict:
     """Measure the saturated capacity on the first n_calibrate requests of the
-    stream, then serve n_requests arriving at load * capacity."""
+    stream, then serve n_requests arriving at load * capacity.  Each entry of
+    extra_loads serves the same stream again at that multiple of the capacity
+    (e.g. 2.0: overload) and is reported under "at_load_<x>"."""
     calib = W.serve_requests(n_calibrate, seed=seed, rate=1.0, steps=steps)
     cap = saturated_capacity(calib, arena_bytes)
-    rate = load * cap["req_per_s"]
-    reqs = W.serve_requests(n_requests, seed=seed, rate=rate, steps=steps)
-    res = run(reqs, arena_bytes)
-    res.update({"rate_req_per_s": rate, "load": load, "capacity_req_per_s": cap["req_per_s"],
-                "capacity_mlups": cap["mlups"], "seed": seed, "steps_per_request": steps})
-    return res
+    out = None
+    for i, ld in enumerate((load,) + tuple(extra_loads)):
+        rate = ld * cap["req_per_s"]
+        reqs = W.serve_requests(n_requests, seed=seed, rate=rate, steps=steps)
+        res = run(reqs, arena_bytes)
+        res.update({"rate_req_per_s": rate, "load": ld, "capacity_req_per_s": cap["req_per_s"],
+                    "capacity_mlups": cap["mlups"], "seed": seed, "steps_per_request": steps})
+        if i == 0:
+            out = res
+        else:
+            out[f"at_load_{ld:g}"] = {k: res[k] for k in ("p50_s", "p99_s", "mean_s", "mlups", "max_active",
+                                                          "rate_req_per_s", "wall_s")}
+    return out

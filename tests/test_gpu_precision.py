@@ -1,0 +1,83 @@
+"""FP32 deviation storage against FP64 plain storage on the GPU (64^3, one free
+sphere, velocity Verlet): the same seeded system stepped in both precisions.
+
+Reported: the sphere's velocity history V(t), species drift in each precision,
+the FP32-vs-FP64 difference of every field, the FP32/FP64 speedup at this size.
+
+Two regimes.  While both runs cover the same cells, the difference is FP32
+rounding: V agrees to ~1e-5 over the first 300 steps.  Later the sphere
+positions (FP64 on both sides, driven by forces summed from FP32 fields)
+differ by ~1e-6 cells, and discrete events -- a cell covered, a depth-4 Psi
+leaf centre crossing the surface -- happen one step apart in the two runs;
+each such event moves the solute near the surface and kicks the sphere, and V
+then differs by up to a few 1e-3 and near-surface densities by ~1e-3 (the
+oracle comparisons of single steps bound the arithmetic itself much more
+tightly).  Both precisions conserve each species (FP64 to 1e-12, FP32 to
+1e-6)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1607_04572_amd import workloads as W
+from parity_util import make_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.mean((a - b) ** 2)) / max(np.sqrt(np.mean(b ** 2)), 1e-300))
+
+
+@pytest.mark.timeout(600)
+def test_c1_fp32_against_fp64():
+    steps, every = 1000, 100
+    out = {}
+    for prec in ("fp64", "fp32"):
+        w = W.c1(prec)
+        say(f"case {w.name}")
+        g = make_gpu(w)
+        g.prepare()
+        t_init = np.asarray(g.diagnostics()["species_total"][:2])
+        vt = []
+        g.step(1)
+        g.sync()
+        t0 = time.perf_counter()
+        for _ in range(steps // every):
+            g.step(every)
+            vt.append(g.particles()[0]["v"].copy())
+        g.sync()
+        dt = time.perf_counter() - t0
+        out[prec] = dict(V=np.array(vt), flag=g.field("flag"), density=g.field("density"), phi=g.field("phi"),
+                         velocity=g.field("velocity"), populations=g.field("populations"),
+                         drift=np.abs(np.asarray(g.diagnostics()["species_total"][:2]) / t_init - 1).max(),
+                         ms_per_step=dt / steps * 1e3)
+        g.close()
+    a, b = out["fp32"], out["fp64"]
+    fluid = (a["flag"] == 0) & (b["flag"] == 0)
+    N = fluid.size
+    err = {
+        "density": rel_rms(a["density"].reshape(2, N)[:, fluid], b["density"].reshape(2, N)[:, fluid]),
+        "phi": rel_rms(a["phi"], b["phi"]),
+        "velocity": rel_rms(a["velocity"].reshape(3, N)[:, fluid], b["velocity"].reshape(3, N)[:, fluid]),
+        "populations": rel_rms(a["populations"].reshape(19, N)[:, fluid], b["populations"].reshape(19, N)[:, fluid]),
+        "V": float(np.max(np.linalg.norm(a["V"] - b["V"], axis=1) / np.linalg.norm(b["V"], axis=1))),
+    }
+    say("V(t) fp64 x-component every 100 steps:", np.array2string(b["V"][:, 0], precision=6))
+    say("|V32 - V64| / |V64| every 100 steps:",
+        np.array2string(np.linalg.norm(a["V"] - b["V"], axis=1) / np.linalg.norm(b["V"], axis=1), precision=2))
+    fl = fluid.reshape(w.shape[2], w.shape[1], w.shape[0])
+    d32 = a["density"].reshape(2, *fl.shape)[0]
+    d64 = b["density"].reshape(2, *fl.shape)[0]
+    dd = np.abs(d32 - d64) * fl
+    zz, yy, xx = np.unravel_index(np.argmax(dd), dd.shape)
+    say("largest density difference", f"{dd.max():.3e}", "at cell", (int(xx), int(yy), int(zz)))
+    say("fp32 vs fp64:", {k: f"{v:.2e}" for k, v in err.items()},
+        "drift fp32", f"{a['drift']:.2e}", "fp64", f"{b['drift']:.2e}",
+        "ms/step fp32", f"{a['ms_per_step']:.3f}", "fp64", f"{b['ms_per_step']:.3f}",
+        "speedup", f"{b['ms_per_step'] / a['ms_per_step']:.2f}")
+    assert b["drift"] < 1e-12 and a["drift"] < 1e-6
+    dv = np.linalg.norm(a["V"] - b["V"], axis=1) / np.linalg.norm(b["V"], axis=1)
+    assert np.all(dv[:3] < 1e-4), dv
+    assert err["V"] < 1e-2
+    assert err["density"] < 1e-2 and err["phi"] < 1e-2 and err["velocity"] < 5e-2 and err["populations"] < 1e-4
