@@ -63,7 +63,7 @@ Layout make_layout(const ek_params* p, size_t ts) {
     int mp = p->max_particles > 0 ? p->max_particles : 1;
     L.parts = take((size_t)mp * sizeof(PState));
     L.state_end = off;
-    L.spec = take((size_t)(p->nx / 2 + 1) * p->ny * p->nz * 2 * ts);
+    L.spec = take((size_t)spec_stride(p->nx, (int)ts) * p->ny * p->nz * 2 * ts);
     L.tw = take((size_t)(p->nx + p->ny + p->nz) * 2 * ts);
     L.k2 = take((size_t)(p->nx + p->ny + p->nz) * ts);
     L.scratch = take((size_t)DIAG_BLOCKS * NDIAG * sizeof(double));
@@ -149,8 +149,9 @@ void setup_sim(ek_ctx* c, Sim<T>& s) {
     s.ny = p->ny;
     s.nz = p->nz;
     s.nxh = p->nx / 2 + 1;
+    s.nxs = spec_stride(p->nx, (int)sizeof(T));
     s.N = N;
-    s.Nspec = (long)s.nxh * p->ny * p->nz;
+    s.Nspec = (long)s.nxs * p->ny * p->nz;
     s.ns = p->n_species;
     s.np = 0;
     s.pv = p->scheme == EK_SCHEME_PARTIAL_VOLUME;

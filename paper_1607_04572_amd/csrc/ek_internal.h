@@ -98,6 +98,7 @@ struct PState {
 template <typename T>
 struct Sim {
     int nx, ny, nz, nxh;
+    int nxs;                  // row stride of the half spectrum (nxh rounded up to 128-byte lines)
     long N, Nspec;
     int ns, np;
     int pv, charge_mode, integrator;
@@ -146,6 +147,15 @@ __host__ __device__ inline int fft_tile_kx(int n, int elem_bytes) {
     int cap = (FFT_THREADS * FFT_ELEMS) / n;
     int t = elem_bytes == 4 ? 16 : 8;
     return t < cap ? t : cap;
+}
+// Row stride of the half spectrum: nx/2 + 1 complex values rounded up to whole
+// 128-byte lines, so that every column tile of the y and z passes starts on a
+// line (an odd stride splits each tile row over two lines and doubles the
+// traffic of those passes).
+__host__ __device__ inline int spec_stride(int nx, int elem_bytes) {
+    const int per_line = 128 / (2 * elem_bytes);
+    const int nh = nx / 2 + 1;
+    return (nh + per_line - 1) / per_line * per_line;
 }
 // EK tiles: TXW x TYW cells per z-plane, ZC planes per workgroup.
 template <typename T> struct EKTile {

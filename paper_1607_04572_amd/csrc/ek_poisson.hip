@@ -8,7 +8,8 @@
 // (neutralising background), and transformed back.  Five passes over HBM:
 //   X  : charge assembly + real-to-half-complex FFT along x.  Two real rows
 //        (y, y+1) form one complex sequence; their spectra are separated by
-//        Hermitian symmetry.  Writes the half spectrum S[z][y][kx].
+//        Hermitian symmetry.  Writes the half spectrum S[z][y][kx] (row stride
+//        nxs >= nx/2 + 1, whole 128-byte lines).
 //   Y  : complex FFT along y of tiles of consecutive kx (coalesced rows).
 //   Z  : complex FFT along z, Green's function (with the 1/N scale), inverse
 //        FFT along z, all in LDS.
@@ -304,8 +305,8 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
         cpx<T> q1 = mk<T>((T)0.5 * (A.x + B.x), (T)0.5 * (A.y - B.y));
         cpx<T> q2 = mk<T>((T)0.5 * (A.y + B.y), (T)-0.5 * (A.x - B.x));
         long row = 2 * pr;
-        S[row * nh + k] = q1;
-        S[(row + 1) * nh + k] = q2;
+        S[row * s.nxs + k] = q1;
+        S[(row + 1) * s.nxs + k] = q2;
     }
 }
 
@@ -335,10 +336,10 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
         if (pr < npairs) {
             long row = 2 * pr;
             if (k < nh) {
-                cpx<T> q1 = S[row * nh + k], q2 = S[(row + 1) * nh + k];
+                cpx<T> q1 = S[row * s.nxs + k], q2 = S[(row + 1) * s.nxs + k];
                 v = mk<T>(q1.x - q2.y, q1.y + q2.x);  // q1 + i q2
             } else {
-                cpx<T> q1 = S[row * nh + (n - k)], q2 = S[(row + 1) * nh + (n - k)];
+                cpx<T> q1 = S[row * s.nxs + (n - k)], q2 = S[(row + 1) * s.nxs + (n - k)];
                 v = mk<T>(q1.x + q2.y, -q1.y + q2.x);  // conj(q1) + i conj(q2)
             }
         }
@@ -376,18 +377,18 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int by_, in
     // columns of this tile: TX, fewer in the last one (the Nyquist column alone
     // when nh = n/2 + 1 is one more than a multiple of TX)
     const int TC = nh - kx0 < TX ? nh - kx0 : TX;
-    cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec) + (long)z * n * nh;
+    cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec) + (long)z * n * s.nxs;
     const FDiv dtc(TC);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[1], n);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
         int y = dtc.div(t), i = t - y * TC;
-        a[i * ld + y] = S[(long)y * nh + kx0 + i];
+        a[i * ld + y] = S[(long)y * s.nxs + kx0 + i];
     }
     __syncthreads();
     fft_any<T, INV>(a, n, TC, ld, tw);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
         int y = dtc.div(t), i = t - y * TC;
-        S[(long)y * nh + kx0 + i] = a[i * ld + y];
+        S[(long)y * s.nxs + kx0 + i] = a[i * ld + y];
     }
 }
 
@@ -409,12 +410,12 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
     int kx0 = (bx_ - ky * tiles) * TX;
     const int TC = nh - kx0 < TX ? nh - kx0 : TX;  // columns of this tile
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
-    const long zstride = (long)ny * nh;
+    const long zstride = (long)ny * s.nxs;
     const FDiv dtc(TC), dn(n);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[2], n);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
         int z = dtc.div(t), i = t - z * TC;
-        a[i * ld + z] = S[z * zstride + (long)ky * nh + kx0 + i];
+        a[i * ld + z] = S[z * zstride + (long)ky * s.nxs + kx0 + i];
     }
     __syncthreads();
     fft_any<T, false>(a, n, TC, ld, tw);
@@ -431,7 +432,7 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
     fft_any<T, true>(a, n, TC, ld, tw);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
         int z = dtc.div(t), i = t - z * TC;
-        S[z * zstride + (long)ky * nh + kx0 + i] = a[i * ld + z];
+        S[z * zstride + (long)ky * s.nxs + kx0 + i] = a[i * ld + z];
     }
 }
 
