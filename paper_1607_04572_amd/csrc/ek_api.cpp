@@ -49,7 +49,7 @@ Layout make_layout(const ek_params* p, size_t ts) {
         off += align256(bytes);
         return o;
     };
-    L.f = take(2 * 19 * N * ts);
+    L.f = take(2 * 19 * (size_t)fpad((long)N) * ts);
     L.rho = take(2 * (size_t)p->n_species * N * ts);
     L.u = take(2 * 3 * N * ts);
     L.fext = take(3 * N * ts);
@@ -176,7 +176,7 @@ void setup_sim(ek_ctx* c, Sim<T>& s) {
     s.n_wall = 0;
     size_t ts = sizeof(T);
     s.f[0] = (T*)(A + L.f);
-    s.f[1] = s.f[0] + 19 * N;
+    s.f[1] = s.f[0] + 19 * fpad(N);
     s.rho[0] = (T*)(A + L.rho);
     s.rho[1] = s.rho[0] + (long)p->n_species * N;
     s.u[0] = (T*)(A + L.u);
@@ -214,7 +214,7 @@ int init_fields(ek_ctx* c, Sim<T>& s) {
     long N = c->N;
     bool dev = sizeof(T) == 4;
     for (int b = 0; b < 2; ++b)
-        for (int i = 0; i < 19; ++i) fill<T>(s.f[b] + (long)i * N, N, dev ? (T)0 : (T)q19w(i), st);
+        fill_pops<T>(s.f[b], fpad(N), dev, st);
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < p->n_species; ++k)
             fill<T>(s.rho[b] + (long)k * N, N,
@@ -468,7 +468,8 @@ int get_field(ek_ctx* c, Sim<T>& s, int field, void* host, size_t bytes) {
         case EK_FIELD_FLUID_DENSITY: src = s.f[cur]; break;
         case EK_FIELD_PARTICLE_CHARGE: src = s.rhob; break;
     }
-    long nsrc = field == EK_FIELD_FLUID_DENSITY ? 19 * N : ne;
+    const bool pops = field == EK_FIELD_POPULATIONS || field == EK_FIELD_FLUID_DENSITY;
+    long nsrc = pops ? 19 * fpad(N) : ne;  // populations: the blocked layout
     h.resize(nsrc);
     HIPCHK(c, hipMemcpy(h.data(), src, nsrc * sizeof(T), hipMemcpyDeviceToHost));
     if (field == EK_FIELD_DENSITY) {
@@ -476,11 +477,11 @@ int get_field(ek_ctx* c, Sim<T>& s, int field, void* host, size_t bytes) {
             for (long i = 0; i < N; ++i) o[k * N + i] = ((dev ? s.rho_ref[k] : 0.0) + (double)h[k * N + i]) * fac;
     } else if (field == EK_FIELD_POPULATIONS) {
         for (int q = 0; q < 19; ++q)
-            for (long i = 0; i < N; ++i) o[q * N + i] = ((dev ? q19w(q) : 0.0) + (double)h[q * N + i]) * fac;
+            for (long i = 0; i < N; ++i) o[q * N + i] = ((dev ? q19w(q) : 0.0) + (double)h[fidx(q, i)]) * fac;
     } else if (field == EK_FIELD_FLUID_DENSITY) {
         for (long i = 0; i < N; ++i) {
             double m = dev ? 1.0 : 0.0;
-            for (int q = 0; q < 19; ++q) m += (double)h[q * N + i];
+            for (int q = 0; q < 19; ++q) m += (double)h[fidx(q, i)];
             o[i] = m * fac;
         }
     } else {
@@ -509,9 +510,12 @@ int set_field(ek_ctx* c, Sim<T>& s, int field, const void* host, size_t bytes) {
                 for (long i = 0; i < N; ++i) h[k * N + i] = (T)(in[k * N + i] / fac - (dev ? s.rho_ref[k] : 0.0));
             break;
         case EK_FIELD_POPULATIONS:
+            // to the blocked layout; the padding cells hold the rest state
             dst = s.f[cur];
+            h.assign(19 * fpad(N), (T)0);
+            for (long e = 0; e < 19 * fpad(N); ++e) h[e] = dev ? (T)0 : (T)q19w((int)((e / FB) % 19));
             for (int q = 0; q < 19; ++q)
-                for (long i = 0; i < N; ++i) h[q * N + i] = (T)(in[q * N + i] / fac - (dev ? q19w(q) : 0.0));
+                for (long i = 0; i < N; ++i) h[fidx(q, i)] = (T)(in[q * N + i] / fac - (dev ? q19w(q) : 0.0));
             break;
         case EK_FIELD_PHI: dst = s.phi; break;
         case EK_FIELD_VELOCITY: dst = s.u[cur]; break;
@@ -520,7 +524,7 @@ int set_field(ek_ctx* c, Sim<T>& s, int field, const void* host, size_t bytes) {
     }
     if (field == EK_FIELD_PHI || field == EK_FIELD_VELOCITY || field == EK_FIELD_FORCE)
         for (long i = 0; i < ne; ++i) h[i] = (T)(in[i] / fac);
-    HIPCHK(c, hipMemcpyAsync(dst, h.data(), ne * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return EK_OK;
 }

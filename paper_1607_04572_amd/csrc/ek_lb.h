@@ -86,7 +86,7 @@ __device__ __forceinline__ void lb_pull(const Sim<T>& s, const Nbr& nb, T (&fi)[
     const T* __restrict__ fs = s.f[s.cur];
     sfor<19>([&](auto I) {
         constexpr int i = I;
-        fi[i] = ld32(fs + (long)i * s.N, nb.src32(i));
+        fi[i] = fs[fidx(i, nb.src32(i))];
     });
 }
 
@@ -129,7 +129,7 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
                         vb[2] = q.v[2] + (q.w[0] * r[1] - q.w[1] * r[0]);
                     }
                     double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
-                    fi[i] = ld32(fs + (long)q19opp(i) * s.N, c) + (T)(6.0 * q19w(i) * cv);
+                    fi[i] = fs[fidx(q19opp(i), c)] + (T)(6.0 * q19w(i) * cv);
                 }
             }
         });
@@ -152,10 +152,11 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
     const T le = s.lam_e, lo = s.lam_o;
     const T g2 = (T)2 + le;
     const T uf3 = uf / (T)3;
+    T* __restrict__ fc = fd + fidx(0, c);  // population i of cell c at fc[i * FB]
     {  // rest population: even part only
         const T w = (T)q19w(0);
         const T feq_e = w * (rho - (T)1.5 * usq);
-        st32_nt(fd, c, fi[0] + le * (fi[0] - feq_e) + (T)4.5 * w * g2 * (-uf3));
+        __builtin_nontemporal_store(fi[0] + le * (fi[0] - feq_e) + (T)4.5 * w * g2 * (-uf3), fc);
     }
     // TRT per pair: the even part (symmetric relaxation and the even forcing
     // term) is shared by i and ibar, the odd part changes sign.
@@ -168,8 +169,8 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
         const T feq_e = w * (rho + (T)4.5 * cu * cu - (T)1.5 * usq);
         const T ev = le * ((T)0.5 * ps[i] - feq_e) + (T)4.5 * w * g2 * (cu * cf - uf3);
         const T od = lo * ((T)0.5 * pd[i] - (T)3 * w * cj) + (T)3 * w * cf;
-        st32_nt(fd + (long)i * s.N, c, fi[i] + ev + od);
-        st32_nt(fd + (long)o * s.N, c, fi[o] + ev - od);
+        __builtin_nontemporal_store(fi[i] + ev + od, fc + i * FB);
+        __builtin_nontemporal_store(fi[o] + ev - od, fc + o * FB);
     });
     st32_nt(uo, c, ux);
     st32_nt(uo + s.N, c, uy);

@@ -470,7 +470,7 @@ __global__ __launch_bounds__(PT) void k_geometry(Sim<T> s, int init) {
 
 template <typename T>
 __device__ __forceinline__ double pop_abs(const Sim<T>& s, const T* f, int i, long c, double wi) {
-    return sizeof(T) == 4 ? wi + (double)f[(long)i * s.N + c] : (double)f[(long)i * s.N + c];
+    return sizeof(T) == 4 ? wi + (double)f[fidx(i, c)] : (double)f[fidx(i, c)];
 }
 
 template <typename T>
@@ -547,7 +547,7 @@ __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_,
                     if (stable(s.flag[n])) {
                         double rn = 0.0;
                         // density of the neighbour (as a deviation from 1 on the FP32 path)
-                        sfor<19>([&](auto J) { rn += (double)f[(long)J * s.N + n]; });
+                        sfor<19>([&](auto J) { rn += (double)f[fidx(J, n)]; });
                         sum += rn;
                         nf++;
                     }
@@ -568,7 +568,7 @@ __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_,
                 double cu = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
                 double feq = w * (rbar + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
                 T st = (T)feq;
-                f[(long)i * s.N + c] = st;
+                f[fidx(i, c)] = st;
                 double back = (double)st;
                 pf[0] += back * q19x(i);
                 pf[1] += back * q19y(i);

@@ -21,6 +21,24 @@ void fill(T* p, long n, T v, hipStream_t st) {
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(UT), 0, st, p, n, v);
 }
+// Rest-state populations in the blocked layout: f = w_i (FP64 plain) or 0 (FP32
+// deviations) over n_pad cells.
+template <typename T>
+__global__ void k_fill_pops(T* f, long npad, bool dev) {
+    const long e = (long)blockIdx.x * UT + threadIdx.x;
+    if (e >= 19 * npad) return;
+    const int i = (int)((e / FB) % 19);
+    f[e] = dev ? (T)0 : (T)q19w(i);
+}
+
+template <typename T>
+void fill_pops(T* f, long npad, bool dev, hipStream_t st) {
+    long blocks = (19 * npad + UT - 1) / UT;
+    hipLaunchKernelGGL(k_fill_pops<T>, dim3((unsigned)blocks), dim3(UT), 0, st, f, npad, dev);
+}
+template void fill_pops<float>(float*, long, bool, hipStream_t);
+template void fill_pops<double>(double*, long, bool, hipStream_t);
+
 template void fill<float>(float*, long, float, hipStream_t);
 template void fill<double>(double*, long, double, hipStream_t);
 template void fill<uint8_t>(uint8_t*, long, uint8_t, hipStream_t);
@@ -44,7 +62,7 @@ __global__ __launch_bounds__(UT) void k_diag_stage1(Sim<T> s) {
         double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
         sfor<19>([&](auto I) {
             constexpr int i = I;
-            double fi = (DEV ? q19w(i) : 0.0) + (double)f[(long)i * s.N + c];
+            double fi = (DEV ? q19w(i) : 0.0) + (double)f[fidx(i, c)];
             m += fi;
             jx += fi * q19x(i);
             jy += fi * q19y(i);
