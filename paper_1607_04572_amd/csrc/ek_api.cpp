@@ -51,8 +51,8 @@ Layout make_layout(const ek_params* p, size_t ts) {
     };
     L.f = take(2 * 19 * (size_t)fpad((long)N) * ts);
     L.rho = take(2 * (size_t)p->n_species * N * ts);
-    L.u = take(2 * 3 * N * ts);
-    L.fext = take(3 * N * ts);
+    L.u = take(2 * 3 * (size_t)fpad((long)N) * ts);
+    L.fext = take(3 * (size_t)fpad((long)N) * ts);
     L.phi = take(N * ts);
     L.rhob = take(N * ts);
     L.psi = take(N * sizeof(float));
@@ -180,7 +180,7 @@ void setup_sim(ek_ctx* c, Sim<T>& s) {
     s.rho[0] = (T*)(A + L.rho);
     s.rho[1] = s.rho[0] + (long)p->n_species * N;
     s.u[0] = (T*)(A + L.u);
-    s.u[1] = s.u[0] + 3 * N;
+    s.u[1] = s.u[0] + 3 * fpad(N);
     s.fext = (T*)(A + L.fext);
     s.phi = (T*)(A + L.phi);
     s.rhob = (T*)(A + L.rhob);
@@ -219,8 +219,8 @@ int init_fields(ek_ctx* c, Sim<T>& s) {
         for (int k = 0; k < p->n_species; ++k)
             fill<T>(s.rho[b] + (long)k * N, N,
                     dev ? (T)0 : (T)(p->species[k].mean_density * p->agrid * p->agrid * p->agrid), st);
-    fill<T>(s.u[0], 2 * 3 * N, (T)0, st);
-    fill<T>(s.fext, 3 * N, (T)0, st);
+    fill<T>(s.u[0], 2 * 3 * fpad(N), (T)0, st);
+    fill<T>(s.fext, 3 * fpad(N), (T)0, st);
     fill<T>(s.phi, N, (T)0, st);
     fill<T>(s.rhob, N, (T)0, st);
     fill<float>(s.psi, N, 0.0f, st);
@@ -469,7 +469,9 @@ int get_field(ek_ctx* c, Sim<T>& s, int field, void* host, size_t bytes) {
         case EK_FIELD_PARTICLE_CHARGE: src = s.rhob; break;
     }
     const bool pops = field == EK_FIELD_POPULATIONS || field == EK_FIELD_FLUID_DENSITY;
-    long nsrc = pops ? 19 * fpad(N) : ne;  // populations: the blocked layout
+    const bool vec = field == EK_FIELD_VELOCITY || field == EK_FIELD_FORCE;
+    // populations, velocity and force are stored in blocks of FB cells
+    long nsrc = pops ? 19 * fpad(N) : (vec ? 3 * fpad(N) : ne);
     h.resize(nsrc);
     HIPCHK(c, hipMemcpy(h.data(), src, nsrc * sizeof(T), hipMemcpyDeviceToHost));
     if (field == EK_FIELD_DENSITY) {
@@ -484,6 +486,9 @@ int get_field(ek_ctx* c, Sim<T>& s, int field, void* host, size_t bytes) {
             for (int q = 0; q < 19; ++q) m += (double)h[fidx(q, i)];
             o[i] = m * fac;
         }
+    } else if (vec) {
+        for (int d = 0; d < 3; ++d)
+            for (long i = 0; i < N; ++i) o[d * N + i] = (double)h[vidx(d, i)] * fac;
     } else {
         for (long i = 0; i < ne; ++i) o[i] = (double)h[i] * fac;
     }
@@ -522,8 +527,13 @@ int set_field(ek_ctx* c, Sim<T>& s, int field, const void* host, size_t bytes) {
         case EK_FIELD_FORCE: dst = s.fext; break;
         default: return EK_ERR_INVALID_ARG;
     }
-    if (field == EK_FIELD_PHI || field == EK_FIELD_VELOCITY || field == EK_FIELD_FORCE)
+    if (field == EK_FIELD_PHI)
         for (long i = 0; i < ne; ++i) h[i] = (T)(in[i] / fac);
+    if (field == EK_FIELD_VELOCITY || field == EK_FIELD_FORCE) {
+        h.assign(3 * fpad(N), (T)0);
+        for (int d = 0; d < 3; ++d)
+            for (long i = 0; i < N; ++i) h[vidx(d, i)] = (T)(in[d * N + i] / fac);
+    }
     HIPCHK(c, hipMemcpyAsync(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return EK_OK;

@@ -217,9 +217,10 @@ __device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, T
         uint8_t fl = ld32(s.flag, c);
         r.v[NS] = ld32(s.phi, c);
         r.v[NS + 1] = (T)psi;
-        r.v[NS + 2] = ld32(ui, c);
-        r.v[NS + 3] = ld32(ui + s.N, c);
-        r.v[NS + 4] = ld32(ui + 2 * s.N, c);
+        const T* uc = ui + vidx(0, c);
+        r.v[NS + 2] = uc[0];
+        r.v[NS + 3] = uc[FB];
+        r.v[NS + 4] = uc[2 * FB];
         r.v[NS + 5] = (fl & F_CUR) ? (T)1 : (T)0;
 #pragma unroll
         for (int k = NS + 6; k < RecEK<T, NS>::NV; ++k) r.v[k] = (T)0;
@@ -371,9 +372,10 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
                 else out = sh.elem(s0, ctr, k) + dr[k];
                 st32_nt(rout + (long)k * s.N, c, out);
             }
-            st32_nt(s.fext, c, fe[0]);
-            st32_nt(s.fext + s.N, c, fe[1]);
-            st32_nt(s.fext + 2 * s.N, c, fe[2]);
+            T* fc = s.fext + vidx(0, c);
+            __builtin_nontemporal_store(fe[0], fc);
+            __builtin_nontemporal_store(fe[1], fc + FB);
+            __builtin_nontemporal_store(fe[2], fc + 2 * FB);
             if constexpr (FUSE) {
                 if (wall) {
                     lb_wall(s, c);

@@ -158,6 +158,12 @@ __host__ __device__ __forceinline__ size_t fidx(int i, size_t c) {
     return (c / FB) * (size_t)(19 * FB) + (size_t)i * FB + (c % FB);
 }
 
+// The velocity and the force density use the same blocking for their three
+// components, v[c / FB][d][c % FB].
+__host__ __device__ __forceinline__ size_t vidx(int d, size_t c) {
+    return (c / FB) * (size_t)(3 * FB) + (size_t)d * FB + (c % FB);
+}
+
 // Row stride of the half spectrum: nx/2 + 1 complex values rounded up to whole
 // 128-byte lines, so that every column tile of the y and z passes starts on a
 // line (an odd stride splits each tile row over two lines and doubles the

@@ -172,18 +172,19 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
         __builtin_nontemporal_store(fi[i] + ev + od, fc + i * FB);
         __builtin_nontemporal_store(fi[o] + ev - od, fc + o * FB);
     });
-    st32_nt(uo, c, ux);
-    st32_nt(uo + s.N, c, uy);
-    st32_nt(uo + 2 * s.N, c, uz);
+    T* uc = uo + vidx(0, c);
+    __builtin_nontemporal_store(ux, uc);
+    __builtin_nontemporal_store(uy, uc + FB);
+    __builtin_nontemporal_store(uz, uc + 2 * FB);
 }
 
 // Velocity of a boundary cell (no populations are streamed there).
 template <typename T>
 __device__ __forceinline__ void lb_wall(const Sim<T>& s, uint32_t c) {
-    T* __restrict__ uo = s.u[s.cur ^ 1];
-    st32_nt(uo, c, (T)0);
-    st32_nt(uo + s.N, c, (T)0);
-    st32_nt(uo + 2 * s.N, c, (T)0);
+    T* __restrict__ uc = s.u[s.cur ^ 1] + vidx(0, c);
+    __builtin_nontemporal_store((T)0, uc);
+    __builtin_nontemporal_store((T)0, uc + FB);
+    __builtin_nontemporal_store((T)0, uc + 2 * FB);
 }
 
 // Launch geometry of the stand-alone LB kernel: workgroup b covers cells

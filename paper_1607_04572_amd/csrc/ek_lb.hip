@@ -22,7 +22,8 @@ __device__ __forceinline__ void lb_body(const Sim<T>& s, int bx_, int by_, int g
     T fi[19];
     lb_pull(s, nb, fi);
     const uint8_t fl = ld32(s.flag, c);
-    const T fx = ld32(s.fext, c), fy = ld32(s.fext + s.N, c), fz = ld32(s.fext + 2 * s.N, c);
+    const T* fc = s.fext + vidx(0, c);
+    const T fx = fc[0], fy = fc[FB], fz = fc[2 * FB];
     if (fl & F_CUR) {
         lb_wall(s, c);
         return;

@@ -72,8 +72,8 @@ __global__ __launch_bounds__(UT) void k_diag_stage1(Sim<T> s) {
         acc[MAXS + 2] += jx;
         acc[MAXS + 3] += jy;
         acc[MAXS + 4] += jz;
-        const T* u = s.u[s.cur];
-        double ux = u[c], uy = u[s.N + c], uz = u[2 * s.N + c];
+        const T* u = s.u[s.cur] + vidx(0, c);
+        double ux = u[0], uy = u[FB], uz = u[2 * FB];
         double um = sqrt(ux * ux + uy * uy + uz * uz);
         acc[MAXS + 6] = um > acc[MAXS + 6] ? um : acc[MAXS + 6];
     }
