@@ -273,22 +273,44 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
     const T* rho = s.rho[s.cur];
     const FDiv dn(n), dnh(s.nxh);
     const cpx<T>* tw = stage_twiddles<T>(a, P * ld, s.tw[0], n);
-    for (int t = threadIdx.x; t < P * n; t += FT) {
-        int pen = dn.div(t), x = t - pen * n;
-        int pr = pair0 + pen;
-        cpx<T> v = mk<T>(0, 0);
-        if (pr < npairs) {
-            int row = 2 * pr;  // row = y + ny*z with y even
-            long c0 = (long)row * n + x, c1 = c0 + n;
-            T q0 = s.rhob[c0], q1 = s.rhob[c1];
-            for (int k = 0; k < s.ns; ++k) {
-                T zk = (T)s.z[k];
-                q0 += zk * rho[(long)k * s.N + c0];
-                q1 += zk * rho[(long)k * s.N + c1];
+    // P n <= FT FE / 2: at most XIT elements per thread; every load is issued
+    // before the first LDS store (a loop that stores as it loads would wait
+    // for each element's loads in turn)
+    constexpr int XIT = FE / 2;
+    long cr[XIT];
+    T q0[XIT], q1[XIT];
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+        const int t = threadIdx.x + it * FT;
+        cr[it] = -1;
+        q0[it] = q1[it] = (T)0;
+        if (t < P * n) {
+            const int pen = dn.div(t), x = t - pen * n, pr = pair0 + pen;
+            if (pr < npairs) {
+                cr[it] = (long)(2 * pr) * n + x;  // row 2 pr = y + ny z with y even
+                q0[it] = s.rhob[cr[it]];
+                q1[it] = s.rhob[cr[it] + n];
             }
-            v = mk<T>(q0, q1);
         }
-        a[pen * ld + x] = v;
+    }
+    for (int k = 0; k < s.ns; ++k) {
+        const T zk = (T)s.z[k];
+        const T* rk = rho + (long)k * s.N;
+#pragma unroll
+        for (int it = 0; it < XIT; ++it) {
+            if (cr[it] >= 0) {
+                q0[it] += zk * rk[cr[it]];
+                q1[it] += zk * rk[cr[it] + n];
+            }
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+        const int t = threadIdx.x + it * FT;
+        if (t < P * n) {
+            const int pen = dn.div(t), x = t - pen * n;
+            a[pen * ld + x] = mk<T>(q0[it], q1[it]);
+        }
     }
     __syncthreads();
     fft_any<T, false>(a, n, P, ld, tw);
@@ -329,21 +351,32 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
     const cpx<T>* S = reinterpret_cast<const cpx<T>*>(s.spec);
     const FDiv dn(n);
     const cpx<T>* tw = stage_twiddles<T>(a, P * ld, s.tw[0], n);
-    for (int t = threadIdx.x; t < P * n; t += FT) {
-        int pen = dn.div(t), k = t - pen * n;
-        int pr = pair0 + pen;
-        cpx<T> v = mk<T>(0, 0);
-        if (pr < npairs) {
-            long row = 2 * pr;
-            if (k < nh) {
-                cpx<T> q1 = S[row * s.nxs + k], q2 = S[(row + 1) * s.nxs + k];
-                v = mk<T>(q1.x - q2.y, q1.y + q2.x);  // q1 + i q2
-            } else {
-                cpx<T> q1 = S[row * s.nxs + (n - k)], q2 = S[(row + 1) * s.nxs + (n - k)];
-                v = mk<T>(q1.x + q2.y, -q1.y + q2.x);  // conj(q1) + i conj(q2)
+    // loads first, as in the forward pass (P n <= FT FE / 2)
+    constexpr int XIT = FE / 2;
+    cpx<T> q1[XIT], q2[XIT];
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+        const int t = threadIdx.x + it * FT;
+        q1[it] = q2[it] = mk<T>(0, 0);
+        if (t < P * n) {
+            const int pen = dn.div(t), k = t - pen * n, pr = pair0 + pen;
+            if (pr < npairs) {
+                const long row = 2 * pr;
+                const int kk = k < nh ? k : n - k;
+                q1[it] = S[row * s.nxs + kk];
+                q2[it] = S[(row + 1) * s.nxs + kk];
             }
         }
-        a[pen * ld + k] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+        const int t = threadIdx.x + it * FT;
+        if (t < P * n) {
+            const int pen = dn.div(t), k = t - pen * n;
+            const cpx<T> a1 = q1[it], a2 = q2[it];
+            // k < nh: q1 + i q2; otherwise conj(q1) + i conj(q2) of the mirrored column
+            a[pen * ld + k] = k < nh ? mk<T>(a1.x - a2.y, a1.y + a2.x) : mk<T>(a1.x + a2.y, -a1.y + a2.x);
+        }
     }
     __syncthreads();
     fft_any<T, true>(a, n, P, ld, tw);
@@ -363,6 +396,42 @@ __global__ __launch_bounds__(FT) void k_fft_x_inv(Sim<T> s, int P) {
     fft_x_inv_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, P);
 }
 
+// Tile of TC columns x n rows from the spectrum into LDS, a[i * ld + row] =
+// get(row, i); consecutive threads take consecutive columns of a row.  In FP64
+// every thread's loads (at most FE: TC n <= FT FE) are issued before its first
+// LDS store; in FP32 that costs more registers (and occupancy) than it saves
+// and the plain loop is faster (both measured).
+template <typename T, typename G>
+__device__ __forceinline__ void load_tile(cpx<T>* a, int ld, int TC, int n, const FDiv& dtc, G&& get) {
+    if constexpr (sizeof(T) == 8) {
+        T vx[FE], vy[FE];
+#pragma unroll
+        for (int it = 0; it < FE; ++it) {
+            const int t = threadIdx.x + it * FT;
+            vx[it] = vy[it] = (T)0;
+            if (t < TC * n) {
+                const int r = dtc.div(t), i = t - r * TC;
+                const cpx<T> v = get(r, i);
+                vx[it] = v.x;
+                vy[it] = v.y;
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < FE; ++it) {
+            const int t = threadIdx.x + it * FT;
+            if (t < TC * n) {
+                const int r = dtc.div(t), i = t - r * TC;
+                a[i * ld + r] = mk<T>(vx[it], vy[it]);
+            }
+        }
+    } else {
+        for (int t = threadIdx.x; t < TC * n; t += FT) {
+            const int r = dtc.div(t), i = t - r * TC;
+            a[i * ld + r] = get(r, i);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Pass Y (forward or inverse): pencils along y, TX consecutive kx per group.
 // ---------------------------------------------------------------------------
@@ -380,10 +449,7 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int by_, in
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec) + (long)z * n * s.nxs;
     const FDiv dtc(TC);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[1], n);
-    for (int t = threadIdx.x; t < TC * n; t += FT) {
-        int y = dtc.div(t), i = t - y * TC;
-        a[i * ld + y] = S[(long)y * s.nxs + kx0 + i];
-    }
+    load_tile<T>(a, ld, TC, n, dtc, [&](int y, int i) { return S[(long)y * s.nxs + kx0 + i]; });
     __syncthreads();
     fft_any<T, INV>(a, n, TC, ld, tw);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
@@ -413,10 +479,7 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
     const long zstride = (long)ny * s.nxs;
     const FDiv dtc(TC), dn(n);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[2], n);
-    for (int t = threadIdx.x; t < TC * n; t += FT) {
-        int z = dtc.div(t), i = t - z * TC;
-        a[i * ld + z] = S[z * zstride + (long)ky * s.nxs + kx0 + i];
-    }
+    load_tile<T>(a, ld, TC, n, dtc, [&](int z, int i) { return S[z * zstride + (long)ky * s.nxs + kx0 + i]; });
     __syncthreads();
     fft_any<T, false>(a, n, TC, ld, tw);
     const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
