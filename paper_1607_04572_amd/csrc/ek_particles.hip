@@ -32,8 +32,8 @@ constexpr int PT = 256;  // threads per particle workgroup
 // (rounding is monotone), and a box decided outside has leaves whose squared
 // distance exceeds its near-point bound by at least 1/1024, far beyond
 // rounding.  The GPU therefore classifies the whole cell first and, for cells
-// cut by the surface, counts leaf centres with a full wavefront: lane l takes
-// the leaf columns (i, j) = l, l+64, l+128, l+192 of the 16 x 16 grid.
+// cut by the surface, counts leaf centres with 16 lanes per cell (a wavefront
+// resolves four cut cells at a time).
 // ---------------------------------------------------------------------------
 // Level-0 classification: 4096 (inside), 0 (outside) or -1 (cut by the surface).
 __device__ __forceinline__ int psi_cell_class(double lx, double ly, double lz, double R2) {
@@ -50,11 +50,14 @@ __device__ __forceinline__ int psi_cell_class(double lx, double ly, double lz, d
     return -1;
 }
 
-// Leaf-centre count of one cut cell, computed by the whole wavefront (all 64
-// lanes must call it with the same arguments).
-__device__ __forceinline__ int wave_leaf_count(double lx, double ly, double lz, double R2) {
+// Leaf-centre count of a cut cell by a group of 16 lanes (the four groups of
+// a wavefront count four cells at once): lane j of the group takes the leaf
+// columns (i, j), i = 0..15, of the 16 x 16 grid.  The count is an integer,
+// so the order of the partial sums does not matter.  Returns the group's total
+// in every lane of the group.
+__device__ __forceinline__ int group_leaf_count(double lx, double ly, double lz, double R2) {
 #pragma clang fp contract(off)
-    const int lane = threadIdx.x & 63;
+    const int j = threadIdx.x & 15;
     double cz2[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -67,13 +70,13 @@ __device__ __forceinline__ int wave_leaf_count(double lx, double ly, double lz, 
         czmin = cz2[k] < czmin ? cz2[k] : czmin;
         czmax = cz2[k] > czmax ? cz2[k] : czmax;
     }
+    const double cy = ly + (double)(2 * j + 1) * 0.03125;
+    const double cy2 = cy * cy;
     int cnt = 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        int col = lane + 64 * r;
-        double cx = lx + (double)(2 * (col >> 4) + 1) * 0.03125;
-        double cy = ly + (double)(2 * (col & 15) + 1) * 0.03125;
-        double sxy = cx * cx + cy * cy;
+    for (int i = 0; i < 16; ++i) {
+        double cx = lx + (double)(2 * i + 1) * 0.03125;
+        double sxy = cx * cx + cy2;
         if (sxy + czmin > R2) continue;       // no leaf of this column inside (monotone)
         if (sxy + czmax <= R2) {              // every leaf of this column inside
             cnt += 16;
@@ -83,22 +86,33 @@ __device__ __forceinline__ int wave_leaf_count(double lx, double ly, double lz, 
         for (int k = 0; k < 16; ++k) cnt += (sxy + cz2[k] <= R2) ? 1 : 0;
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    for (int off = 8; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
     return cnt;
 }
 
 // Cooperative Psi count: every lane of the wavefront calls this together; a
 // lane with need == true receives the count of its cell (lx, ly, lz = cell
-// corner relative to the sphere centre).
+// corner relative to the sphere centre).  Pending cells are taken four at a
+// time, one per 16-lane group.
 __device__ __forceinline__ int wave_psi_resolve(bool need, double lx, double ly, double lz, double R2, int mine) {
     unsigned long long mask = __ballot(need);
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, g = lane >> 4;
     while (mask) {
-        int l = __ffsll((long long)mask) - 1;
-        double bx = __shfl(lx, l), by = __shfl(ly, l), bz = __shfl(lz, l), br = __shfl(R2, l);
-        int c = wave_leaf_count(bx, by, bz, br);
-        if (lane == l) mine = c;
-        mask &= mask - 1;
+        int src[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            src[q] = mask ? __ffsll((long long)mask) - 1 : -1;
+            mask = mask ? mask & (mask - 1) : mask;
+        }
+        const int l = g == 0 ? src[0] : (g == 1 ? src[1] : (g == 2 ? src[2] : src[3]));
+        const int ls = l < 0 ? lane : l;  // groups without a cell count their own (discarded)
+        const double bx = __shfl(lx, ls), by = __shfl(ly, ls), bz = __shfl(lz, ls), br = __shfl(R2, ls);
+        const int c = group_leaf_count(bx, by, bz, br);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cq = __shfl(c, 16 * q);
+            if (src[q] == lane) mine = cq;
+        }
     }
     return mine;
 }
@@ -414,8 +428,13 @@ __device__ __forceinline__ void geometry_body(const Sim<T>& s, int bx_, int by_,
     build_nbrs(s, me, L);
     const int nn = nbr_count(L, s.np);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int base = bx_ * PT + wave * 64; base < me.ncell; base += gx_ * PT) {
-        int t = base + lane;
+    // The lanes of a wavefront take box cells Wn apart (Wn = wavefronts per
+    // particle), so that every wavefront samples the whole box: cut cells, each
+    // resolved by a whole wavefront in turn, are then spread evenly over the
+    // wavefronts instead of piling up in those whose cells lie on the surface.
+    const int G = gx_ * PT, Wn = G / 64, wg = bx_ * (PT / 64) + wave;
+    for (int base = 0; base < me.ncell; base += G) {
+        int t = base + lane * Wn + wg;
         int x = 0, y = 0, z = 0;
         bool active = t < me.ncell;
         if (active) {
