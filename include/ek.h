@@ -200,12 +200,11 @@ int ek_set_state(ek_ctx* c, const void* host, size_t bytes);
 #define EK_STAGE_GEOMETRY 1  /* flags, owners, Psi, particle charge */
 #define EK_STAGE_BOUNDARY 2  /* Aidun destroy/create, expel, refill, pool */
 #define EK_STAGE_POISSON 3   /* charge assembly + 5 FFT passes */
-#define EK_STAGE_HYDRO 4     /* momentum-exchange force (reads the populations before streaming) */
+#define EK_STAGE_FORCES 4    /* momentum-exchange (populations before streaming) and electrostatic forces */
 #define EK_STAGE_EK 5        /* link fluxes, continuity, coupling force; in FP64 also stream/collide (fused) */
 #define EK_STAGE_LB 6        /* stream/collide as its own kernel (FP32); 0 where fused into EK_STAGE_EK */
-#define EK_STAGE_FORCES 7    /* electrostatic force */
-#define EK_STAGE_FINISH 8    /* closing kick */
-#define EK_N_STAGES 9
+#define EK_STAGE_FINISH 7    /* closing kick */
+#define EK_N_STAGES 8
 int ek_profile_stages(ek_ctx* c, int n, double* ms_out, int n_out);
 
 /* Bandwidth probe: a plain device-to-device copy kernel of `bytes` (a

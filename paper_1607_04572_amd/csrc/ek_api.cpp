@@ -245,18 +245,20 @@ int init_fields(ek_ctx* c, Sim<T>& s) {
     return EK_OK;
 }
 
+// One step.  In a chain of steps (a captured graph), `moved`: the previous
+// step's closing kernel already performed this step's kick and drift;
+// `chain`: this step's closing kernel performs the next step's.
 template <typename T>
-void enqueue_step(const ek_ctx* c, Sim<T> s) {
+void enqueue_step(const ek_ctx* c, Sim<T> s, bool moved = false, bool chain = false) {
     hipStream_t st = c->stream;
-    launch_move(s, st, 0);
+    if (!moved) launch_move(s, st, 0);
     launch_geometry(s, st, 0);
     launch_boundary(s, st);
     if (!s.pv) launch_refill(s, st);
     launch_charge_poisson(s, st);
-    launch_hydro(s, st);
+    launch_particle_forces(s, st);
     launch_fields(s, st);
-    launch_forces(s, st);
-    launch_finish(s, st);
+    launch_finish(s, st, chain);
 }
 
 // One step with a HIP event recorded after each stage (instrumentation).
@@ -273,14 +275,12 @@ void enqueue_step_timed(const ek_ctx* c, Sim<T> s, hipEvent_t* ev) {
     (void)hipEventRecord(ev[3], st);
     launch_charge_poisson(s, st);
     (void)hipEventRecord(ev[4], st);
-    launch_hydro(s, st);
+    launch_particle_forces(s, st);
     (void)hipEventRecord(ev[5], st);
     launch_fields(s, st, ev[6]);
     (void)hipEventRecord(ev[7], st);
-    launch_forces(s, st);
-    (void)hipEventRecord(ev[8], st);
     launch_finish(s, st);
-    (void)hipEventRecord(ev[9], st);
+    (void)hipEventRecord(ev[8], st);
 }
 
 template <typename T>
@@ -313,7 +313,7 @@ int build_graph(ek_ctx* c, Sim<T> s, int parity, int nsteps, hipGraphExec_t* out
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < nsteps; ++k) {
         s.cur = (parity + k) & 1;
-        enqueue_step(c, s);
+        enqueue_step(c, s, k > 0, k < nsteps - 1);
     }
     HIPCHK(c, hipStreamEndCapture(c->stream, &g));
     hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -1006,9 +1006,9 @@ int push_table(ek_batch* b) {
 void enqueue_batch_step(ek_batch* b) {
     launch_batch_particles_pre(b->dtab, b->stream);
     launch_batch_poisson(b->dtab, b->stream);
-    launch_batch_hydro(b->dtab, b->stream);
+    launch_batch_particle_forces(b->dtab, b->stream);
     launch_batch_fields(b->dtab, b->ns, b->stream);
-    launch_batch_particles_post(b->dtab, b->stream);
+    launch_batch_finish(b->dtab, b->stream);
     launch_batch_flip(b->dtab, b->stream);
 }
 

@@ -278,14 +278,16 @@ template <typename T> void launch_hydro(const Sim<T>& s, hipStream_t st);
 template <typename T> void launch_forces(const Sim<T>& s, hipStream_t st);
 template <typename T> void fill(T* p, long n, T v, hipStream_t st);
 template <typename T> void fill_pops(T* f, long npad, bool dev, hipStream_t st);
-template <typename T> void launch_finish(const Sim<T>& s, hipStream_t st);
+template <typename T> void launch_particle_forces(const Sim<T>& s, hipStream_t st);  // hydro + electrostatic
+// closing kick; and_move: also the next step's kick and drift (inside a chain of steps)
+template <typename T> void launch_finish(const Sim<T>& s, hipStream_t st, bool and_move = false);
 template <typename T> void launch_diagnostics(const Sim<T>& s, hipStream_t st, double* out);
 // batched step pieces (FP32 tables)
 void launch_batch_particles_pre(const BatchTable* tab, hipStream_t st);
 void launch_batch_poisson(const BatchTable* tab, hipStream_t st);
 void launch_batch_fields(const BatchTable* tab, int ns, hipStream_t st);
-void launch_batch_hydro(const BatchTable* tab, hipStream_t st);
-void launch_batch_particles_post(const BatchTable* tab, hipStream_t st);
+void launch_batch_particle_forces(const BatchTable* tab, hipStream_t st);
+void launch_batch_finish(const BatchTable* tab, hipStream_t st);
 void launch_batch_flip(BatchTable* tab, hipStream_t st);
 void launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
 

@@ -359,10 +359,8 @@ __device__ __forceinline__ double* partial_rec(const Sim<T>& s, int kind, int p,
 // Particle move (Sec. III.B) and box of this step.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void move_body(const Sim<T>& s, int bx_, int by_, int gx_, int init) {
+__device__ __forceinline__ void move_particle(const Sim<T>& s, int p, int init) {
 #pragma clang fp contract(off)
-    int p = bx_ * blockDim.x + threadIdx.x;
-    if (p >= s.np) return;
     PState& q = s.parts[p];
     double L[3] = {(double)s.nx, (double)s.ny, (double)s.nz};
     double xold[3] = {q.x[0], q.x[1], q.x[2]};
@@ -404,6 +402,12 @@ __device__ __forceinline__ void move_body(const Sim<T>& s, int bx_, int by_, int
     }
     for (int k = 0; k < MAXS; ++k) q.pool[k] = 0.0;
     q.ncov = q.nvac = q.npool = q.nflag = 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void move_body(const Sim<T>& s, int bx_, int by_, int gx_, int init) {
+    const int p = bx_ * blockDim.x + threadIdx.x;
+    if (p < s.np) move_particle(s, p, init);
 }
 
 template <typename T>
@@ -885,7 +889,7 @@ __global__ __launch_bounds__(PT) void k_el_force(Sim<T> s) {
 // workgroup per particle: lane k < 12 sums component k of the hydrodynamic and
 // electrostatic chunk partials in chunk order (deterministic).
 template <typename T>
-__device__ __forceinline__ void finish_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+__device__ __forceinline__ void finish_body(const Sim<T>& s, int bx_, int by_, int gx_, bool and_move = false) {
 #pragma clang fp contract(off)
     const int p = bx_, k = threadIdx.x;
     __shared__ double sum[12];
@@ -926,11 +930,22 @@ __device__ __forceinline__ void finish_body(const Sim<T>& s, int bx_, int by_, i
         q.F[d] = Fn[d];
         q.T[d] = Tn[d];
     }
+    // inside a chain of steps the next step's kick and drift follow at once
+    if (and_move) move_particle(s, p, 0);
 }
 
 template <typename T>
-__global__ void k_finish(Sim<T> s) {
-    finish_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+__global__ void k_finish(Sim<T> s, int and_move) {
+    finish_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, and_move != 0);
+}
+
+// Momentum-exchange and electrostatic forces in one launch (after the Poisson
+// solve: the first reads the populations, which nothing writes before the LB
+// update; the second the potential).
+template <typename T>
+__global__ __launch_bounds__(PT) void k_particle_forces(Sim<T> s) {
+    hydro_force_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+    el_force_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1075,15 +1090,21 @@ void launch_forces(const Sim<T>& s, hipStream_t st) {
 }
 
 template <typename T>
+void launch_particle_forces(const Sim<T>& s, hipStream_t st) {
+    if (s.np == 0) return;
+    hipLaunchKernelGGL(k_particle_forces<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
+}
+
+template <typename T>
 void launch_hydro(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
     hipLaunchKernelGGL(k_hydro_force<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
 }
 
 template <typename T>
-void launch_finish(const Sim<T>& s, hipStream_t st) {
+void launch_finish(const Sim<T>& s, hipStream_t st, bool and_move) {
     if (s.np == 0) return;
-    hipLaunchKernelGGL(k_finish<T>, dim3(s.np), dim3(64), 0, st, s);
+    hipLaunchKernelGGL(k_finish<T>, dim3(s.np), dim3(64), 0, st, s, and_move ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1123,13 +1144,9 @@ __global__ __launch_bounds__(PT) void kb_refill_stable(const BatchTable* tab) {
         if (!s.pv) refill_stable_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
-__global__ __launch_bounds__(PT) void kb_hydro_force(const BatchTable* tab) {
+__global__ __launch_bounds__(PT) void kb_particle_forces(const BatchTable* tab) {
     batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
         hydro_force_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
-    });
-}
-__global__ __launch_bounds__(PT) void kb_el_force(const BatchTable* tab) {
-    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
         el_force_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
@@ -1147,15 +1164,13 @@ void launch_batch_particles_pre(const BatchTable* tab, hipStream_t st) {
     hipLaunchKernelGGL(kb_refill_stable, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
 }
 
-void launch_batch_particles_post(const BatchTable* tab, hipStream_t st) {
-    hipLaunchKernelGGL(kb_el_force, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
-    hipLaunchKernelGGL(kb_finish, dim3(BATCH_SMALL_BLOCKS), dim3(64), 0, st, tab);
+// after the Poisson solve and before the field update (see k_particle_forces)
+void launch_batch_particle_forces(const BatchTable* tab, hipStream_t st) {
+    hipLaunchKernelGGL(kb_particle_forces, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
 }
 
-// the momentum exchange reads the populations before the LB overwrites the
-// other buffer; it is launched with the post-Poisson group by the host
-void launch_batch_hydro(const BatchTable* tab, hipStream_t st) {
-    hipLaunchKernelGGL(kb_hydro_force, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+void launch_batch_finish(const BatchTable* tab, hipStream_t st) {
+    hipLaunchKernelGGL(kb_finish, dim3(BATCH_SMALL_BLOCKS), dim3(64), 0, st, tab);
 }
 
 #define EK_INST(T)                                                     \
@@ -1166,7 +1181,8 @@ void launch_batch_hydro(const BatchTable* tab, hipStream_t st) {
     template void launch_refill<T>(const Sim<T>&, hipStream_t);        \
     template void launch_forces<T>(const Sim<T>&, hipStream_t);        \
     template void launch_hydro<T>(const Sim<T>&, hipStream_t);         \
-    template void launch_finish<T>(const Sim<T>&, hipStream_t);
+    template void launch_particle_forces<T>(const Sim<T>&, hipStream_t); \
+    template void launch_finish<T>(const Sim<T>&, hipStream_t, bool);
 EK_INST(float)
 EK_INST(double)
 

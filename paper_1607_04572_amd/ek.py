@@ -77,7 +77,7 @@ SYMBOLS = ["ek_query_footprint", "ek_create", "ek_add_sphere", "ek_set_static_bo
            "ek_prepare", "ek_step", "ek_get_fields", "ek_get_particles", "ek_get_diagnostics",
            "ek_get_state", "ek_set_state", "ek_profile_stages", "ek_copy_probe", "ek_synchronize",
            "ek_destroy", "ek_strerror"]
-STAGES = ["move", "geometry", "boundary", "poisson", "hydro", "ek", "lb", "forces", "finish"]
+STAGES = ["move", "geometry", "boundary", "poisson", "forces", "ek", "lb", "finish"]
 BATCH_SYMBOLS = ["ek_batch_create", "ek_batch_admit", "ek_batch_step", "ek_batch_poll", "ek_batch_collect",
                  "ek_batch_get_fields", "ek_batch_active", "ek_batch_destroy"]
 
