@@ -136,6 +136,9 @@ constexpr int FFT_THREADS = 512;
 constexpr int FFT_ELEMS = 8;    // pencil elements per thread of an FFT workgroup
 constexpr int POOL_BLOCKS = 64;
 
+// LDS stride of an FFT pencil of length n: room for the padded indices
+// i + i/8 (i < n), rounded up to an odd number of elements.
+__host__ __device__ inline int fft_ld(int n) { return (n + (n - 1) / 8 + 1) | 1; }
 // Pencils per workgroup in the x passes (P * n <= 2048).
 __host__ __device__ inline int fft_pencils_x(int n) {
     int P = (FFT_THREADS * FFT_ELEMS / 2) / n;

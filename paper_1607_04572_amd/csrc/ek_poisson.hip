@@ -114,6 +114,13 @@ __device__ __forceinline__ void dft_small(cpx<T> (&v)[R]) {
 constexpr int FT = FFT_THREADS;  // threads per FFT workgroup
 constexpr int FE = FFT_ELEMS;    // pencil elements per thread (P * n <= FT * FE)
 
+// LDS layout of a pencil: element i sits at pad(i) = i + i/8, which spreads the
+// butterfly outputs of a radix-8 stage (lanes 8 or 64 elements apart) over all
+// banks, and pencils are an odd number fft_ld(n) of elements apart, so that
+// the writes of a column tile (consecutive lanes in consecutive pencils) do
+// not share banks either.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, const cpx<T>* __restrict__ tw) {
     constexpr int NB = (FE + R - 1) / R;
@@ -122,7 +129,7 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
     const int nb = P * nR;
     const FDiv dnR(nR), dNs(Ns);
     cpx<T> v[NB][R];
-    int dst[NB];
+    int dst[NB], pens[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         int b = threadIdx.x + q * FT;
@@ -133,7 +140,7 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
             const cpx<T>* src = a + pen * ld;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                cpx<T> x = src[j + r * nR];
+                cpx<T> x = src[pad(j + r * nR)];
                 if (r > 0 && k > 0) {
                     cpx<T> w = tw[k * r * span];
                     if (INV) w.y = -w.y;
@@ -141,7 +148,8 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
                 }
                 v[q][r] = x;
             }
-            dst[q] = pen * ld + jq * Ns * R + k;
+            dst[q] = jq * Ns * R + k;
+            pens[q] = pen * ld;
         }
     }
     __syncthreads();
@@ -150,7 +158,7 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
         if (dst[q] >= 0) {
             dft_small<T, R, INV>(v[q]);
 #pragma unroll
-            for (int r = 0; r < R; ++r) a[dst[q] + r * Ns] = v[q][r];
+            for (int r = 0; r < R; ++r) a[pens[q] + pad(dst[q] + r * Ns)] = v[q][r];
         }
     }
     __syncthreads();
@@ -164,7 +172,7 @@ __device__ __forceinline__ void stage_c(cpx<T>* a, int P, int ld, const cpx<T>* 
     constexpr int nR = N / R, span = N / (NS * R);
     const int nb = P * nR;
     cpx<T> v[NB][R];
-    int dst[NB];
+    int dst[NB], pens[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int b = threadIdx.x + q * FT;
@@ -175,7 +183,7 @@ __device__ __forceinline__ void stage_c(cpx<T>* a, int P, int ld, const cpx<T>* 
             const cpx<T>* src = a + pen * ld;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                cpx<T> x = src[j + r * nR];
+                cpx<T> x = src[pad(j + r * nR)];
                 if (NS > 1 && r > 0 && k > 0) {
                     cpx<T> w = tw[k * r * span];
                     if (INV) w.y = -w.y;
@@ -183,7 +191,8 @@ __device__ __forceinline__ void stage_c(cpx<T>* a, int P, int ld, const cpx<T>* 
                 }
                 v[q][r] = x;
             }
-            dst[q] = pen * ld + jq * NS * R + k;
+            dst[q] = jq * NS * R + k;
+            pens[q] = pen * ld;
         }
     }
     __syncthreads();
@@ -192,7 +201,7 @@ __device__ __forceinline__ void stage_c(cpx<T>* a, int P, int ld, const cpx<T>* 
         if (dst[q] >= 0) {
             dft_small<T, R, INV>(v[q]);
 #pragma unroll
-            for (int r = 0; r < R; ++r) a[dst[q] + r * NS] = v[q][r];
+            for (int r = 0; r < R; ++r) a[pens[q] + pad(dst[q] + r * NS)] = v[q][r];
         }
     }
     __syncthreads();
@@ -267,7 +276,7 @@ template <typename T>
 __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_, int gx_, int P) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int n = s.nx, ld = n + 1;
+    const int n = s.nx, ld = fft_ld(n);
     const int npairs = s.ny * s.nz / 2;
     const int pair0 = bx_ * P;
     const T* rho = s.rho[s.cur];
@@ -309,7 +318,7 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
         const int t = threadIdx.x + it * FT;
         if (t < P * n) {
             const int pen = dn.div(t), x = t - pen * n;
-            a[pen * ld + x] = mk<T>(q0[it], q1[it]);
+            a[pen * ld + pad(x)] = mk<T>(q0[it], q1[it]);
         }
     }
     __syncthreads();
@@ -321,8 +330,8 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
         int pen = dnh.div(t), k = t - pen * nh;
         int pr = pair0 + pen;
         if (pr >= npairs) continue;
-        cpx<T> A = r[pen * ld + k];
-        cpx<T> B = r[pen * ld + (k == 0 ? 0 : n - k)];
+        cpx<T> A = r[pen * ld + pad(k)];
+        cpx<T> B = r[pen * ld + pad(k == 0 ? 0 : n - k)];
         // Q1 = (A + conj B)/2, Q2 = (A - conj B)/(2i)
         cpx<T> q1 = mk<T>((T)0.5 * (A.x + B.x), (T)0.5 * (A.y - B.y));
         cpx<T> q2 = mk<T>((T)0.5 * (A.y + B.y), (T)-0.5 * (A.x - B.x));
@@ -344,7 +353,7 @@ template <typename T>
 __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_, int gx_, int P) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int n = s.nx, ld = n + 1;
+    const int n = s.nx, ld = fft_ld(n);
     const int nh = s.nxh;
     const int npairs = s.ny * s.nz / 2;
     const int pair0 = bx_ * P;
@@ -375,7 +384,7 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
             const int pen = dn.div(t), k = t - pen * n;
             const cpx<T> a1 = q1[it], a2 = q2[it];
             // k < nh: q1 + i q2; otherwise conj(q1) + i conj(q2) of the mirrored column
-            a[pen * ld + k] = k < nh ? mk<T>(a1.x - a2.y, a1.y + a2.x) : mk<T>(a1.x + a2.y, -a1.y + a2.x);
+            a[pen * ld + pad(k)] = k < nh ? mk<T>(a1.x - a2.y, a1.y + a2.x) : mk<T>(a1.x + a2.y, -a1.y + a2.x);
         }
     }
     __syncthreads();
@@ -385,7 +394,7 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
         int pr = pair0 + pen;
         if (pr >= npairs) continue;
         long c0 = (long)(2 * pr) * n + x;
-        cpx<T> v = a[pen * ld + x];
+        cpx<T> v = a[pen * ld + pad(x)];
         s.phi[c0] = v.x;
         s.phi[c0 + n] = v.y;
     }
@@ -421,13 +430,13 @@ __device__ __forceinline__ void load_tile(cpx<T>* a, int ld, int TC, int n, cons
             const int t = threadIdx.x + it * FT;
             if (t < TC * n) {
                 const int r = dtc.div(t), i = t - r * TC;
-                a[i * ld + r] = mk<T>(vx[it], vy[it]);
+                a[i * ld + pad(r)] = mk<T>(vx[it], vy[it]);
             }
         }
     } else {
         for (int t = threadIdx.x; t < TC * n; t += FT) {
             const int r = dtc.div(t), i = t - r * TC;
-            a[i * ld + r] = get(r, i);
+            a[i * ld + pad(r)] = get(r, i);
         }
     }
 }
@@ -438,7 +447,7 @@ __device__ __forceinline__ void load_tile(cpx<T>* a, int ld, int TC, int n, cons
 template <typename T, bool INV>
 __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int by_, int gx_, int TX) {
     extern __shared__ unsigned char smem_raw[];
-    const int n = s.ny, nh = s.nxh, ld = n + 1;
+    const int n = s.ny, nh = s.nxh, ld = fft_ld(n);
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
     int tiles = (nh + TX - 1) / TX;
     int z = bx_ / tiles;
@@ -454,7 +463,7 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int by_, in
     fft_any<T, INV>(a, n, TC, ld, tw);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
         int y = dtc.div(t), i = t - y * TC;
-        S[(long)y * s.nxs + kx0 + i] = a[i * ld + y];
+        S[(long)y * s.nxs + kx0 + i] = a[i * ld + pad(y)];
     }
 }
 
@@ -469,7 +478,7 @@ __global__ __launch_bounds__(FT) void k_fft_y(Sim<T> s, int TX) {
 template <typename T>
 __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int by_, int gx_, int TX) {
     extern __shared__ unsigned char smem_raw[];
-    const int n = s.nz, nh = s.nxh, ny = s.ny, ld = n + 1;
+    const int n = s.nz, nh = s.nxh, ny = s.ny, ld = fft_ld(n);
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
     int tiles = (nh + TX - 1) / TX;
     int ky = bx_ / tiles;
@@ -488,14 +497,14 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int b
         int kx = kx0 + i;
         T K2 = s.k2[0][kx] + s.k2[1][ky] + s.k2[2][kz];
         T g = (kx == 0 && ky == 0 && kz == 0) ? (T)0 : scale / K2;
-        cpx<T> v = a[i * ld + kz];
-        a[i * ld + kz] = mk<T>(v.x * g, v.y * g);
+        cpx<T> v = a[i * ld + pad(kz)];
+        a[i * ld + pad(kz)] = mk<T>(v.x * g, v.y * g);
     }
     __syncthreads();
     fft_any<T, true>(a, n, TC, ld, tw);
     for (int t = threadIdx.x; t < TC * n; t += FT) {
         int z = dtc.div(t), i = t - z * TC;
-        S[z * zstride + (long)ky * s.nxs + kx0 + i] = a[i * ld + z];
+        S[z * zstride + (long)ky * s.nxs + kx0 + i] = a[i * ld + pad(z)];
     }
 }
 
@@ -509,12 +518,12 @@ void launch_charge_poisson(const Sim<T>& s, hipStream_t st) {
     const size_t cs = sizeof(cpx<T>);
     Grids<T> g = grids_of<T>(s);
     int P = fft_pencils_x(s.nx);
-    size_t shx = ((size_t)P * (s.nx + 1) + s.nx) * cs;
+    size_t shx = ((size_t)P * fft_ld(s.nx) + s.nx) * cs;
     hipLaunchKernelGGL(k_fft_x_fwd<T>, dim3(g.n[KK_FFTX]), dim3(FT), shx, st, s, P);
     int TXy = fft_tile_kx(s.ny, sizeof(T)), TXz = fft_tile_kx(s.nz, sizeof(T));
-    size_t shy = ((size_t)TXy * (s.ny + 1) + s.ny) * cs;
+    size_t shy = ((size_t)TXy * fft_ld(s.ny) + s.ny) * cs;
     hipLaunchKernelGGL((k_fft_y<T, false>), dim3(g.n[KK_FFTY]), dim3(FT), shy, st, s, TXy);
-    size_t shz = ((size_t)TXz * (s.nz + 1) + s.nz) * cs;
+    size_t shz = ((size_t)TXz * fft_ld(s.nz) + s.nz) * cs;
     hipLaunchKernelGGL(k_fft_z_green<T>, dim3(g.n[KK_FFTZ]), dim3(FT), shz, st, s, TXz);
     hipLaunchKernelGGL((k_fft_y<T, true>), dim3(g.n[KK_FFTY]), dim3(FT), shy, st, s, TXy);
     hipLaunchKernelGGL(k_fft_x_inv<T>, dim3(g.n[KK_FFTX]), dim3(FT), shx, st, s, P);
@@ -529,7 +538,7 @@ constexpr int BATCH_FFT_BLOCKS = 2048;
 static size_t batch_lds_x() {
     size_t m = 0;
     for (int n = 8; n <= MAX_FFT; n += 2) {
-        size_t v = ((size_t)fft_pencils_x(n) * (n + 1) + n) * sizeof(cpx<float>);
+        size_t v = ((size_t)fft_pencils_x(n) * fft_ld(n) + n) * sizeof(cpx<float>);
         m = v > m ? v : m;
     }
     return m;
@@ -537,7 +546,7 @@ static size_t batch_lds_x() {
 static size_t batch_lds_yz() {
     size_t m = 0;
     for (int n = 8; n <= MAX_FFT; n += 2) {
-        size_t v = ((size_t)fft_tile_kx(n, 4) * (n + 1) + n) * sizeof(cpx<float>);
+        size_t v = ((size_t)fft_tile_kx(n, 4) * fft_ld(n) + n) * sizeof(cpx<float>);
         m = v > m ? v : m;
     }
     return m;
