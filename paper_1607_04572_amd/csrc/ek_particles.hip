@@ -629,14 +629,26 @@ __global__ __launch_bounds__(PT) void k_boundary(Sim<T> s) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void expel_cell(const Sim<T>& s, T* rho, int x, int y, int z, long n) {
+    // The 26 neighbour flags are loaded together first: almost every stable
+    // cell has no covered neighbour and is done after one round of loads.
+    const long ox[3] = {wrap1(x - 1, s.nx), x, wrap1(x + 1, s.nx)};
+    const long oy[3] = {(long)s.nx * wrap1(y - 1, s.ny), (long)s.nx * y, (long)s.nx * wrap1(y + 1, s.ny)};
+    const long nxy = (long)s.nx * s.ny;
+    const long oz[3] = {nxy * wrap1(z - 1, s.nz), nxy * z, nxy * wrap1(z + 1, s.nz)};
+    uint8_t nf[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) nf[q] = q == 13 ? 0 : s.flag[ox[q % 3] + oy[(q / 3) % 3] + oz[q / 9]];
+    unsigned int cov = 0;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) cov |= covered(nf[q]) ? 1u << q : 0u;
+    if (!cov) return;
     double gain[MAXS] = {0.0, 0.0, 0.0, 0.0};
     bool any = false;
     for (int a = -1; a <= 1; ++a)
         for (int b = -1; b <= 1; ++b)
             for (int e = -1; e <= 1; ++e) {
-                if (!(a | b | e)) continue;
+                if (!((cov >> ((a + 1) + 3 * (b + 1) + 9 * (e + 1))) & 1u)) continue;
                 long c = cidx(s, x + a, y + b, z + e);
-                if (!covered(s.flag[c])) continue;
                 int cx = x + a, cy = y + b, cz = z + e;
                 int n19 = 0, n27 = 0;
                 for (int a2 = -1; a2 <= 1; ++a2)
