@@ -528,11 +528,12 @@ __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_,
         int x, y, z;
         bw.cell(s, t, x, y, z);
         long c = cidx(s, x, y, z);
-        uint8_t fl = s.flag[c];
-        if ((fl & F_CUR) && s.owner[c] == p) acc[6 + MAXS + 3] += 1.0;  // n_b
+        const uint8_t fl = s.flag[c];
+        const uint16_t own = s.owner[c];
+        if ((fl & F_CUR) && own == p) acc[6 + MAXS + 3] += 1.0;  // n_b
         if ((fl & (F_CUR | F_PREV)) && !(fl & F_WALL) && box_owner_is(s, L, p, x, y, z)) acc[6 + MAXS + 4] += 1.0;
         if (stable(fl) && box_owner_is(s, L, p, x, y, z)) expel_cell(s, s.rho[s.cur], x, y, z, c);
-        if (covered(fl) && s.owner[c] == p) {
+        if (covered(fl) && own == p) {
             double pf[3] = {0.0, 0.0, 0.0};
             sfor<19>([&](auto I) {
                 constexpr int i = I;
@@ -803,28 +804,41 @@ __device__ __forceinline__ void hydro_force_body(const Sim<T>& s, int bx_, int b
         int x, y, z;
         bw.cell(s, t, x, y, z);
         long b = cidx(s, x, y, z);
-        if (!(s.flag[b] & F_CUR) || s.owner[b] != p) continue;
+        const uint8_t fb = s.flag[b];
+        const uint16_t ob = s.owner[b];
+        if (!(fb & F_CUR) || ob != p) continue;
         double r[3];
         cell_disp(s, x, y, z, me.x, r);
         double vb[3] = {me.v[0] + (me.w[1] * r[2] - me.w[2] * r[1]),
                         me.v[1] + (me.w[2] * r[0] - me.w[0] * r[2]),
                         me.v[2] + (me.w[0] * r[1] - me.w[1] * r[0])};
+        // the 18 neighbour flags and populations in one round of loads; links
+        // into the particle contribute exact zeros
+        uint8_t nfl[19];
+        T pv[19];
         sfor<19>([&](auto I) {
             constexpr int i = I;
             if constexpr (i > 0) {
                 long xf = cidx(s, x - q19x(i), y - q19y(i), z - q19z(i));
-                if (!(s.flag[xf] & F_CUR)) {
-                    constexpr double w = q19w(i);
-                    double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
-                    double tt = 2.0 * pop_abs(s, f, i, xf, w) - 6.0 * w * cv;
-                    double df[3] = {q19x(i) * tt, q19y(i) * tt, q19z(i) * tt};
-                    acc[0] += df[0];
-                    acc[1] += df[1];
-                    acc[2] += df[2];
-                    acc[3] += r[1] * df[2] - r[2] * df[1];
-                    acc[4] += r[2] * df[0] - r[0] * df[2];
-                    acc[5] += r[0] * df[1] - r[1] * df[0];
-                }
+                nfl[i] = s.flag[xf];
+                pv[i] = f[fidx(i, xf)];
+            }
+        });
+        sfor<19>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) {
+                constexpr double w = q19w(i);
+                double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
+                double fi = sizeof(T) == 4 ? w + (double)pv[i] : (double)pv[i];
+                double tt = 2.0 * fi - 6.0 * w * cv;
+                tt = (nfl[i] & F_CUR) ? 0.0 : tt;
+                double df[3] = {q19x(i) * tt, q19y(i) * tt, q19z(i) * tt};
+                acc[0] += df[0];
+                acc[1] += df[1];
+                acc[2] += df[2];
+                acc[3] += r[1] * df[2] - r[2] * df[1];
+                acc[4] += r[2] * df[0] - r[0] * df[2];
+                acc[5] += r[0] * df[1] - r[1] * df[0];
             }
         });
     }
@@ -860,10 +874,13 @@ __device__ __forceinline__ void el_force_body(const Sim<T>& s, int bx_, int by_,
         double d[3] = {0.0, 0.0, 0.0};
         if (active) cell_disp(s, x, y, z, me.x, d);
         if (active && s.charge_mode == EK_CHARGE_UNIFORM) {
-            if ((s.flag[c] & F_CUR) && s.owner[c] == p && me.nb > 0) qb = me.Z / (double)me.nb;
+            const uint8_t fc = s.flag[c];
+            const uint16_t oc = s.owner[c];
+            if ((fc & F_CUR) && oc == p && me.nb > 0) qb = me.Z / (double)me.nb;
         } else if (active) {
-            uint16_t po = s.psi_owner[c];
-            if (po == (uint16_t)p) qb = me.Z * (double)s.psi[c] / me.Vp;
+            const uint16_t po = s.psi_owner[c];
+            const float ps = s.psi[c];
+            if (po == (uint16_t)p) qb = me.Z * (double)ps / me.Vp;
             else if (po == MULTI_OWNER && !far_from(d[0], d[1], d[2], me.R)) need = true;
         }
         // cells overlapped by several spheres: this sphere's own Psi
