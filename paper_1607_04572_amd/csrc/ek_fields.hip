@@ -61,11 +61,19 @@ constexpr double link_coef() { return 1.0 / ((1.0 + 2.0 * 1.4142135623730950488)
 
 // Fraction of a cell moving with velocity u that lands in the neighbour at
 // offset s along one axis: |u| if s has the sign of u, 1 - |u| if s = 0, else 0.
+// In FP32 max(+-u, 0) is one median-of-three instruction, med3(+-u, 0, 1e30)
+// (the plain select or max costs a compare or a NaN-quieting step more; a
+// lattice velocity is far below the bound); the result differs at most in the
+// sign of a zero fraction, which no sum can turn into a value.
 template <typename T, int SX>
 __device__ __forceinline__ T vof_axis(T u) {
-    if constexpr (SX > 0) return u > (T)0 ? u : (T)0;
-    else if constexpr (SX < 0) return u < (T)0 ? -u : (T)0;
-    else return (T)1 - fabs(u);
+    if constexpr (sizeof(T) == 4 && SX != 0) {
+        return __builtin_amdgcn_fmed3f(SX > 0 ? u : -u, 0.0f, 1.0e30f);
+    } else {
+        if constexpr (SX > 0) return u > (T)0 ? u : (T)0;
+        else if constexpr (SX < 0) return u < (T)0 ? -u : (T)0;
+        else return (T)1 - fabs(u);
+    }
 }
 
 // g(s; u) = product over the axes, in axis order.
@@ -107,11 +115,11 @@ struct VofCell {
 template <typename T, bool DEV, int NS, int H, bool CLEAN>
 __device__ __forceinline__ void link_flux(const Sim<T>& s, const RecEK<T, NS>& a, const RecEK<T, NS>& b,
                                           const EKConst<T, NS>& K, const T ga, const T gb, T (&jt)[NS], T& gsum) {
-    gsum = (T)0;
     if constexpr (!CLEAN) {
         if (a.wall() || b.wall()) {
 #pragma unroll
             for (int k = 0; k < NS; ++k) jt[k] = (T)0;
+            gsum = (T)0;
             return;
         }
     }
@@ -148,10 +156,11 @@ __device__ __forceinline__ void link_flux(const Sim<T>& s, const RecEK<T, NS>& a
             // g = (A + mig dphi): the flux over D/(A0|s|); gsum collects it for
             // the friction, which the caller scales by 1/(A0|s|)
             const T g = A + mig * dphi;
-            gsum += g;
+            gsum = k == 0 ? g : gsum + g;
             jt[k] = K.Dc[k][hlen(H) > 1.0 ? 1 : 0] * g + adv;
         } else {
             jt[k] = adv;
+            gsum = (T)0;
         }
     }
 }
@@ -259,17 +268,22 @@ __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T
                                         vof_frac<T, -ox, -oy, -oz>(cu.ux(), cu.uy(), cu.uz()), jt1, g1);
         link_flux<T, DEV, NS, h, CLEAN>(s, cd, me, K, vof_frac<T, ox, oy, oz>(cd.ux(), cd.uy(), cd.uz()),
                                         mv.template frac<-ox, -oy, -oz>(), jt2, g2);
+        // the first term of each sum is assigned (an added 0 is an instruction)
 #pragma unroll
-        for (int k = 0; k < NS; ++k) dr[k] += jt2[k] - jt1[k];
+        for (int k = 0; k < NS; ++k) dr[k] = h == 0 ? jt2[k] - jt1[k] : dr[k] + (jt2[k] - jt1[k]);
         if constexpr (h < 9) {
-            // each link's friction is shared by its two cells (scaled by kT/2 below)
+            // each link's friction is shared by its two cells (scaled by kT/2
+            // below); directions 0, 1, 2 are the unit vectors x, y, z
             const T g = (g1 + g2) * (T)link_coef<h>();
-            if constexpr (ox > 0) fe[0] += g;
-            if constexpr (ox < 0) fe[0] -= g;
-            if constexpr (oy > 0) fe[1] += g;
-            if constexpr (oy < 0) fe[1] -= g;
-            if constexpr (oz > 0) fe[2] += g;
-            if constexpr (oz < 0) fe[2] -= g;
+            if constexpr (h < 3) fe[h] = g;
+            else {
+                if constexpr (ox > 0) fe[0] += g;
+                if constexpr (ox < 0) fe[0] -= g;
+                if constexpr (oy > 0) fe[1] += g;
+                if constexpr (oy < 0) fe[1] -= g;
+                if constexpr (oz > 0) fe[2] += g;
+                if constexpr (oz < 0) fe[2] -= g;
+            }
         }
     });
 }
