@@ -138,15 +138,15 @@ constexpr int POOL_BLOCKS = 64;
 
 // LDS stride of an FFT pencil of length n: room for the padded indices
 // i + i/8 (i < n), rounded up to an odd number of elements.
-__host__ __device__ inline int fft_ld(int n) { return (n + (n - 1) / 8 + 1) | 1; }
+__host__ __device__ constexpr int fft_ld(int n) { return (n + (n - 1) / 8 + 1) | 1; }
 // Pencils per workgroup in the x passes (P * n <= 2048).
-__host__ __device__ inline int fft_pencils_x(int n) {
+__host__ __device__ constexpr int fft_pencils_x(int n) {
     int P = (FFT_THREADS * FFT_ELEMS / 2) / n;
     return P < 1 ? 1 : P;
 }
 // Consecutive kx columns per workgroup in the y and z passes: 16 (FP32) or 8
 // (FP64) for coalesced 128-byte rows, fewer for long pencils (TX * n <= 4096).
-__host__ __device__ inline int fft_tile_kx(int n, int elem_bytes) {
+__host__ __device__ constexpr int fft_tile_kx(int n, int elem_bytes) {
     int cap = (FFT_THREADS * FFT_ELEMS) / n;
     int t = elem_bytes == 4 ? 16 : 8;
     return t < cap ? t : cap;

@@ -166,11 +166,11 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
 
 // The same stage with the length, radix and stride known at compile time
 // (power-of-two lengths): every index is a shift or a mask.
-template <typename T, int N, int R, int NS, bool INV>
+template <typename T, int N, int R, int NS, bool INV, int PC>
 __device__ __forceinline__ void stage_c(cpx<T>* a, int P, int ld, const cpx<T>* __restrict__ tw) {
     constexpr int NB = (FE + R - 1) / R;
     constexpr int nR = N / R, span = N / (NS * R);
-    const int nb = P * nR;
+    const int nb = (PC > 0 ? PC : P) * nR;
     cpx<T> v[NB][R];
     int dst[NB], pens[NB];
 #pragma unroll
@@ -211,12 +211,13 @@ __device__ __forceinline__ void stage_c(cpx<T>* a, int P, int ld, const cpx<T>* 
 template <int M>
 constexpr int radix_of() { return M % 8 == 0 ? 8 : (M % 4 == 0 ? 4 : 2); }
 
-template <typename T, int N, bool INV, int NS = 1>
+// PC > 0: the pencil count is the compile-time PC (P is then ignored).
+template <typename T, int N, bool INV, int PC = 0, int NS = 1>
 __device__ __forceinline__ void fft_lds_c(cpx<T>* a, int P, int ld, const cpx<T>* __restrict__ tw) {
     if constexpr (NS < N) {
         constexpr int R = radix_of<N / NS>();
-        stage_c<T, N, R, NS, INV>(a, P, ld, tw);
-        fft_lds_c<T, N, INV, NS * R>(a, P, ld, tw);
+        stage_c<T, N, R, NS, INV, PC>(a, P, ld, tw);
+        fft_lds_c<T, N, INV, PC, NS * R>(a, P, ld, tw);
     }
 }
 
@@ -257,6 +258,25 @@ __device__ __forceinline__ const cpx<T>* stage_twiddles(cpx<T>* a, int data_elem
 // Compile-time plans for the power-of-two lengths from 32 to 512, the
 // runtime plan otherwise.
 template <typename T, bool INV>
+__device__ __forceinline__ void fft_any(cpx<T>* a, int n, int P, int ld, const cpx<T>* __restrict__ tw);
+
+// Pass bodies are instantiated for a compile-time length NC (a power of two
+// from 32 to 512, or 0: any length, known at run time) and, in the y and z
+// passes, a compile-time group width TCC (0: the width is known at run time).
+// With both known every index of the loads, stages and stores is a shift, a
+// mask or a constant offset.
+template <typename T, bool INV, int NC, int PC>
+__device__ __forceinline__ void fft_n(cpx<T>* a, int n, int P, int ld, const cpx<T>* __restrict__ tw) {
+    if constexpr (NC > 0) fft_lds_c<T, NC, INV, PC>(a, P, ld, tw);
+    else fft_any<T, INV>(a, n, P, ld, tw);
+}
+template <int C>
+__device__ __forceinline__ int cdiv(int t, const FDiv& d) {
+    if constexpr (C > 0) return (int)((unsigned)t / (unsigned)C);
+    else return d.div(t);
+}
+
+template <typename T, bool INV>
 __device__ __forceinline__ void fft_any(cpx<T>* a, int n, int P, int ld, const cpx<T>* __restrict__ tw) {
     switch (n) {
         case 32: fft_lds_c<T, 32, INV>(a, P, ld, tw); break;
@@ -272,15 +292,17 @@ __device__ __forceinline__ void fft_any(cpx<T>* a, int n, int P, int ld, const c
 // Pass X (forward): charge assembly + two-for-one real FFT along x.
 // Work item: a pair of rows (y, y+1) at one z.  P pairs per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_, int gx_, int P) {
+template <typename T, int NC>
+__device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int P_) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int n = s.nx, ld = fft_ld(n);
+    constexpr int PC = NC > 0 ? fft_pencils_x(NC) : 0, NHC = NC > 0 ? NC / 2 + 1 : 0;
+    const int n = NC > 0 ? NC : s.nx, ld = fft_ld(n), P = PC > 0 ? PC : P_;
+    const int nh = NC > 0 ? NHC : s.nxh;
     const int npairs = s.ny * s.nz / 2;
     const int pair0 = bx_ * P;
     const T* rho = s.rho[s.cur];
-    const FDiv dn(n), dnh(s.nxh);
+    const FDiv dn(NC > 0 ? 1 : n), dnh(NC > 0 ? 1 : nh);
     const cpx<T>* tw = stage_twiddles<T>(a, P * ld, s.tw[0], n);
     // P n <= FT FE / 2: at most XIT elements per thread; every load is issued
     // before the first LDS store (a loop that stores as it loads would wait
@@ -294,7 +316,7 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
         cr[it] = -1;
         q0[it] = q1[it] = (T)0;
         if (t < P * n) {
-            const int pen = dn.div(t), x = t - pen * n, pr = pair0 + pen;
+            const int pen = cdiv<NC>(t, dn), x = t - pen * n, pr = pair0 + pen;
             if (pr < npairs) {
                 cr[it] = (long)(2 * pr) * n + x;  // row 2 pr = y + ny z with y even
                 q0[it] = s.rhob[cr[it]];
@@ -317,17 +339,17 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
     for (int it = 0; it < XIT; ++it) {
         const int t = threadIdx.x + it * FT;
         if (t < P * n) {
-            const int pen = dn.div(t), x = t - pen * n;
+            const int pen = cdiv<NC>(t, dn), x = t - pen * n;
             a[pen * ld + pad(x)] = mk<T>(q0[it], q1[it]);
         }
     }
     __syncthreads();
-    fft_any<T, false>(a, n, P, ld, tw);
+    fft_n<T, false, NC, PC>(a, n, P, ld, tw);
     const cpx<T>* r = a;
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
-    const int nh = s.nxh;
+#pragma unroll
     for (int t = threadIdx.x; t < P * nh; t += FT) {
-        int pen = dnh.div(t), k = t - pen * nh;
+        int pen = cdiv<NHC>(t, dnh), k = t - pen * nh;
         int pr = pair0 + pen;
         if (pr >= npairs) continue;
         cpx<T> A = r[pen * ld + pad(k)];
@@ -341,24 +363,20 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int by_
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(FT) void k_fft_x_fwd(Sim<T> s, int P) {
-    fft_x_fwd_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, P);
-}
-
 // ---------------------------------------------------------------------------
 // Pass X' (inverse): two half spectra -> one complex sequence -> two real rows.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_, int gx_, int P) {
+template <typename T, int NC>
+__device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int P_) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int n = s.nx, ld = fft_ld(n);
-    const int nh = s.nxh;
+    constexpr int PC = NC > 0 ? fft_pencils_x(NC) : 0;
+    const int n = NC > 0 ? NC : s.nx, ld = fft_ld(n), P = PC > 0 ? PC : P_;
+    const int nh = NC > 0 ? NC / 2 + 1 : s.nxh;
     const int npairs = s.ny * s.nz / 2;
     const int pair0 = bx_ * P;
     const cpx<T>* S = reinterpret_cast<const cpx<T>*>(s.spec);
-    const FDiv dn(n);
+    const FDiv dn(NC > 0 ? 1 : n);
     const cpx<T>* tw = stage_twiddles<T>(a, P * ld, s.tw[0], n);
     // loads first, as in the forward pass (P n <= FT FE / 2)
     constexpr int XIT = FE / 2;
@@ -368,7 +386,7 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
         const int t = threadIdx.x + it * FT;
         q1[it] = q2[it] = mk<T>(0, 0);
         if (t < P * n) {
-            const int pen = dn.div(t), k = t - pen * n, pr = pair0 + pen;
+            const int pen = cdiv<NC>(t, dn), k = t - pen * n, pr = pair0 + pen;
             if (pr < npairs) {
                 const long row = 2 * pr;
                 const int kk = k < nh ? k : n - k;
@@ -381,16 +399,19 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
     for (int it = 0; it < XIT; ++it) {
         const int t = threadIdx.x + it * FT;
         if (t < P * n) {
-            const int pen = dn.div(t), k = t - pen * n;
+            const int pen = cdiv<NC>(t, dn), k = t - pen * n;
             const cpx<T> a1 = q1[it], a2 = q2[it];
             // k < nh: q1 + i q2; otherwise conj(q1) + i conj(q2) of the mirrored column
             a[pen * ld + pad(k)] = k < nh ? mk<T>(a1.x - a2.y, a1.y + a2.x) : mk<T>(a1.x + a2.y, -a1.y + a2.x);
         }
     }
     __syncthreads();
-    fft_any<T, true>(a, n, P, ld, tw);
-    for (int t = threadIdx.x; t < P * n; t += FT) {
-        int pen = dn.div(t), x = t - pen * n;
+    fft_n<T, true, NC, PC>(a, n, P, ld, tw);
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+        const int t = threadIdx.x + it * FT;
+        if (t >= P * n) continue;
+        int pen = cdiv<NC>(t, dn), x = t - pen * n;
         int pr = pair0 + pen;
         if (pr >= npairs) continue;
         long c0 = (long)(2 * pr) * n + x;
@@ -400,17 +421,12 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int by_
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(FT) void k_fft_x_inv(Sim<T> s, int P) {
-    fft_x_inv_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, P);
-}
-
 // Tile of TC columns x n rows from the spectrum into LDS, a[i * ld + row] =
 // get(row, i); consecutive threads take consecutive columns of a row.  In FP64
 // every thread's loads (at most FE: TC n <= FT FE) are issued before its first
 // LDS store; in FP32 that costs more registers (and occupancy) than it saves
-// and the plain loop is faster (both measured).
-template <typename T, typename G>
+// and the plain loop is faster (both measured).  TCC > 0: TC is that constant.
+template <typename T, int TCC, typename G>
 __device__ __forceinline__ void load_tile(cpx<T>* a, int ld, int TC, int n, const FDiv& dtc, G&& get) {
     if constexpr (sizeof(T) == 8) {
         T vx[FE], vy[FE];
@@ -419,7 +435,7 @@ __device__ __forceinline__ void load_tile(cpx<T>* a, int ld, int TC, int n, cons
             const int t = threadIdx.x + it * FT;
             vx[it] = vy[it] = (T)0;
             if (t < TC * n) {
-                const int r = dtc.div(t), i = t - r * TC;
+                const int r = cdiv<TCC>(t, dtc), i = t - r * TC;
                 const cpx<T> v = get(r, i);
                 vx[it] = v.x;
                 vy[it] = v.y;
@@ -429,14 +445,18 @@ __device__ __forceinline__ void load_tile(cpx<T>* a, int ld, int TC, int n, cons
         for (int it = 0; it < FE; ++it) {
             const int t = threadIdx.x + it * FT;
             if (t < TC * n) {
-                const int r = dtc.div(t), i = t - r * TC;
+                const int r = cdiv<TCC>(t, dtc), i = t - r * TC;
                 a[i * ld + pad(r)] = mk<T>(vx[it], vy[it]);
             }
         }
     } else {
-        for (int t = threadIdx.x; t < TC * n; t += FT) {
-            const int r = dtc.div(t), i = t - r * TC;
-            a[i * ld + pad(r)] = get(r, i);
+#pragma unroll
+        for (int it = 0; it < FE; ++it) {
+            const int t = threadIdx.x + it * FT;
+            if (t < TC * n) {
+                const int r = cdiv<TCC>(t, dtc), i = t - r * TC;
+                a[i * ld + pad(r)] = get(r, i);
+            }
         }
     }
 }
@@ -444,73 +464,158 @@ __device__ __forceinline__ void load_tile(cpx<T>* a, int ld, int TC, int n, cons
 // ---------------------------------------------------------------------------
 // Pass Y (forward or inverse): pencils along y, TX consecutive kx per group.
 // ---------------------------------------------------------------------------
-template <typename T, bool INV>
-__device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int by_, int gx_, int TX) {
+template <typename T, bool INV, int NC, int TCC>
+__device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int TX) {
     extern __shared__ unsigned char smem_raw[];
-    const int n = s.ny, nh = s.nxh, ld = fft_ld(n);
+    const int n = NC > 0 ? NC : s.ny, nh = s.nxh, ld = fft_ld(n);
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
     int tiles = (nh + TX - 1) / TX;
     int z = bx_ / tiles;
     int kx0 = (bx_ - z * tiles) * TX;
     // columns of this tile: TX, fewer in the last one (the Nyquist column alone
     // when nh = n/2 + 1 is one more than a multiple of TX)
-    const int TC = nh - kx0 < TX ? nh - kx0 : TX;
+    const int TC = TCC > 0 ? TCC : (nh - kx0 < TX ? nh - kx0 : TX);
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec) + (long)z * n * s.nxs;
-    const FDiv dtc(TC);
+    const FDiv dtc(TCC > 0 ? 1 : TC);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[1], n);
-    load_tile<T>(a, ld, TC, n, dtc, [&](int y, int i) { return S[(long)y * s.nxs + kx0 + i]; });
+    load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int y, int i) { return S[(long)y * s.nxs + kx0 + i]; });
     __syncthreads();
-    fft_any<T, INV>(a, n, TC, ld, tw);
-    for (int t = threadIdx.x; t < TC * n; t += FT) {
-        int y = dtc.div(t), i = t - y * TC;
+    fft_n<T, INV, NC, TCC>(a, n, TC, ld, tw);
+#pragma unroll
+    for (int it = 0; it < FE; ++it) {
+        const int t = threadIdx.x + it * FT;
+        if (t >= TC * n) break;
+        int y = cdiv<TCC>(t, dtc), i = t - y * TC;
         S[(long)y * s.nxs + kx0 + i] = a[i * ld + pad(y)];
     }
-}
-
-template <typename T, bool INV>
-__global__ __launch_bounds__(FT) void k_fft_y(Sim<T> s, int TX) {
-    fft_y_body<T, INV>(s, blockIdx.x, blockIdx.y, gridDim.x, TX);
 }
 
 // ---------------------------------------------------------------------------
 // Pass Z: forward FFT along z, multiply by the Green's function, inverse FFT.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int by_, int gx_, int TX) {
+template <typename T, int NC, int TCC>
+__device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int TX) {
     extern __shared__ unsigned char smem_raw[];
-    const int n = s.nz, nh = s.nxh, ny = s.ny, ld = fft_ld(n);
+    const int n = NC > 0 ? NC : s.nz, nh = s.nxh, ny = s.ny, ld = fft_ld(n);
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
     int tiles = (nh + TX - 1) / TX;
     int ky = bx_ / tiles;
     int kx0 = (bx_ - ky * tiles) * TX;
-    const int TC = nh - kx0 < TX ? nh - kx0 : TX;  // columns of this tile
+    const int TC = TCC > 0 ? TCC : (nh - kx0 < TX ? nh - kx0 : TX);  // columns of this tile
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec);
     const long zstride = (long)ny * s.nxs;
-    const FDiv dtc(TC), dn(n);
+    const FDiv dtc(TCC > 0 ? 1 : TC), dn(NC > 0 ? 1 : n);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[2], n);
-    load_tile<T>(a, ld, TC, n, dtc, [&](int z, int i) { return S[z * zstride + (long)ky * s.nxs + kx0 + i]; });
+    load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int z, int i) { return S[z * zstride + (long)ky * s.nxs + kx0 + i]; });
     __syncthreads();
-    fft_any<T, false>(a, n, TC, ld, tw);
+    fft_n<T, false, NC, TCC>(a, n, TC, ld, tw);
     const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
-    for (int t = threadIdx.x; t < TC * n; t += FT) {
-        int i = dn.div(t), kz = t - i * n;
+#pragma unroll
+    for (int it = 0; it < FE; ++it) {
+        const int t = threadIdx.x + it * FT;
+        if (t >= TC * n) break;
+        int i = cdiv<NC>(t, dn), kz = t - i * n;
         int kx = kx0 + i;
         T K2 = s.k2[0][kx] + s.k2[1][ky] + s.k2[2][kz];
-        T g = (kx == 0 && ky == 0 && kz == 0) ? (T)0 : scale / K2;
+        // FP32: the hardware reciprocal (1 ulp) instead of a correctly rounded
+        // division; FP64 divides
+        T g;
+        if constexpr (sizeof(T) == 4) g = scale * __builtin_amdgcn_rcpf(K2);
+        else g = scale / K2;
+        g = (kx == 0 && ky == 0 && kz == 0) ? (T)0 : g;
         cpx<T> v = a[i * ld + pad(kz)];
         a[i * ld + pad(kz)] = mk<T>(v.x * g, v.y * g);
     }
     __syncthreads();
-    fft_any<T, true>(a, n, TC, ld, tw);
-    for (int t = threadIdx.x; t < TC * n; t += FT) {
-        int z = dtc.div(t), i = t - z * TC;
+    fft_n<T, true, NC, TCC>(a, n, TC, ld, tw);
+#pragma unroll
+    for (int it = 0; it < FE; ++it) {
+        const int t = threadIdx.x + it * FT;
+        if (t >= TC * n) break;
+        int z = cdiv<TCC>(t, dtc), i = t - z * TC;
         S[z * zstride + (long)ky * s.nxs + kx0 + i] = a[i * ld + pad(z)];
     }
 }
 
+// ---------------------------------------------------------------------------
+// Dispatch on the pencil length: compile-time bodies for the powers of two
+// from 32 to 512 (full groups), the run-time body otherwise.
+// ---------------------------------------------------------------------------
+#define EK_FFT_LENGTHS(X) X(32) X(64) X(128) X(256) X(512)
+
+template <typename T>
+__device__ __forceinline__ void x_fwd_any(const Sim<T>& s, int b, int P) {
+    switch (s.nx) {
+#define EK_CASE(L) \
+    case L: fft_x_fwd_body<T, L>(s, b, P); return;
+        EK_FFT_LENGTHS(EK_CASE)
+#undef EK_CASE
+        default: fft_x_fwd_body<T, 0>(s, b, P);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void x_inv_any(const Sim<T>& s, int b, int P) {
+    switch (s.nx) {
+#define EK_CASE(L) \
+    case L: fft_x_inv_body<T, L>(s, b, P); return;
+        EK_FFT_LENGTHS(EK_CASE)
+#undef EK_CASE
+        default: fft_x_inv_body<T, 0>(s, b, P);
+    }
+}
+// Is group b of a y or z pass a full group of TX columns?
+__device__ __forceinline__ bool full_group(int b, int nh, int TX) {
+    const int tiles = (nh + TX - 1) / TX;
+    return (b % tiles) * TX + TX <= nh;
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void y_any(const Sim<T>& s, int b, int TX) {
+    const bool full = full_group(b, s.nxh, TX);
+    switch (s.ny) {
+#define EK_CASE(L)                                                                   \
+    case L:                                                                          \
+        if (full && TX == fft_tile_kx(L, sizeof(T)))                                 \
+            fft_y_body<T, INV, L, fft_tile_kx(L, sizeof(T))>(s, b, TX);              \
+        else                                                                         \
+            fft_y_body<T, INV, L, 0>(s, b, TX);                                      \
+        return;
+        EK_FFT_LENGTHS(EK_CASE)
+#undef EK_CASE
+        default: fft_y_body<T, INV, 0, 0>(s, b, TX);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void z_any(const Sim<T>& s, int b, int TX) {
+    const bool full = full_group(b, s.nxh, TX);
+    switch (s.nz) {
+#define EK_CASE(L)                                                                   \
+    case L:                                                                          \
+        if (full && TX == fft_tile_kx(L, sizeof(T)))                                 \
+            fft_z_green_body<T, L, fft_tile_kx(L, sizeof(T))>(s, b, TX);             \
+        else                                                                         \
+            fft_z_green_body<T, L, 0>(s, b, TX);                                     \
+        return;
+        EK_FFT_LENGTHS(EK_CASE)
+#undef EK_CASE
+        default: fft_z_green_body<T, 0, 0>(s, b, TX);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(FT) void k_fft_x_fwd(Sim<T> s, int P) {
+    x_fwd_any<T>(s, blockIdx.x, P);
+}
+template <typename T>
+__global__ __launch_bounds__(FT) void k_fft_x_inv(Sim<T> s, int P) {
+    x_inv_any<T>(s, blockIdx.x, P);
+}
+template <typename T, bool INV>
+__global__ __launch_bounds__(FT) void k_fft_y(Sim<T> s, int TX) {
+    y_any<T, INV>(s, blockIdx.x, TX);
+}
 template <typename T>
 __global__ __launch_bounds__(FT) void k_fft_z_green(Sim<T> s, int TX) {
-    fft_z_green_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x, TX);
+    z_any<T>(s, blockIdx.x, TX);
 }
 
 template <typename T>
@@ -552,26 +657,20 @@ static size_t batch_lds_yz() {
     return m;
 }
 
+// (run-time bodies only: the length dispatch inside the batch loop costs
+// registers and spills)
 __global__ __launch_bounds__(FT) void kb_fft_x_fwd(const BatchTable* tab) {
-    batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) {
-        fft_x_fwd_body<float>(s, b, 0, 0, fft_pencils_x(s.nx));
-    });
+    batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) { fft_x_fwd_body<float, 0>(s, b, fft_pencils_x(s.nx)); });
 }
 __global__ __launch_bounds__(FT) void kb_fft_x_inv(const BatchTable* tab) {
-    batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) {
-        fft_x_inv_body<float>(s, b, 0, 0, fft_pencils_x(s.nx));
-    });
+    batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) { fft_x_inv_body<float, 0>(s, b, fft_pencils_x(s.nx)); });
 }
 template <bool INV>
 __global__ __launch_bounds__(FT) void kb_fft_y(const BatchTable* tab) {
-    batch_loop<KK_FFTY>(tab, [](const Sim<float>& s, int b) {
-        fft_y_body<float, INV>(s, b, 0, 0, fft_tile_kx(s.ny, 4));
-    });
+    batch_loop<KK_FFTY>(tab, [](const Sim<float>& s, int b) { fft_y_body<float, INV, 0, 0>(s, b, fft_tile_kx(s.ny, 4)); });
 }
 __global__ __launch_bounds__(FT) void kb_fft_z_green(const BatchTable* tab) {
-    batch_loop<KK_FFTZ>(tab, [](const Sim<float>& s, int b) {
-        fft_z_green_body<float>(s, b, 0, 0, fft_tile_kx(s.nz, 4));
-    });
+    batch_loop<KK_FFTZ>(tab, [](const Sim<float>& s, int b) { fft_z_green_body<float, 0, 0>(s, b, fft_tile_kx(s.nz, 4)); });
 }
 
 void launch_batch_poisson(const BatchTable* tab, hipStream_t st) {
