@@ -314,25 +314,32 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int P_)
     for (int it = 0; it < XIT; ++it) {
         const int t = threadIdx.x + it * FT;
         cr[it] = -1;
-        q0[it] = q1[it] = (T)0;
         if (t < P * n) {
             const int pen = cdiv<NC>(t, dn), x = t - pen * n, pr = pair0 + pen;
-            if (pr < npairs) {
-                cr[it] = (long)(2 * pr) * n + x;  // row 2 pr = y + ny z with y even
-                q0[it] = s.rhob[cr[it]];
-                q1[it] = s.rhob[cr[it] + n];
-            }
+            if (pr < npairs) cr[it] = (long)(2 * pr) * n + x;  // row 2 pr = y + ny z with y even
         }
     }
-    for (int k = 0; k < s.ns; ++k) {
+    // the densities of every species (up to MAXS) requested in one round
+    T d0[MAXS][XIT], d1[MAXS][XIT];
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+        q0[it] = cr[it] >= 0 ? s.rhob[cr[it]] : (T)0;
+        q1[it] = cr[it] >= 0 ? s.rhob[cr[it] + n] : (T)0;
+#pragma unroll
+        for (int k = 0; k < MAXS; ++k) {
+            const T* rk = rho + (long)k * s.N;
+            d0[k][it] = (k < s.ns && cr[it] >= 0) ? rk[cr[it]] : (T)0;
+            d1[k][it] = (k < s.ns && cr[it] >= 0) ? rk[cr[it] + n] : (T)0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MAXS; ++k) {
+        if (k >= s.ns) break;
         const T zk = (T)s.z[k];
-        const T* rk = rho + (long)k * s.N;
 #pragma unroll
         for (int it = 0; it < XIT; ++it) {
-            if (cr[it] >= 0) {
-                q0[it] += zk * rk[cr[it]];
-                q1[it] += zk * rk[cr[it] + n];
-            }
+            q0[it] += zk * d0[k][it];
+            q1[it] += zk * d1[k][it];
         }
     }
 #pragma unroll
