@@ -164,44 +164,64 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
     __syncthreads();
 }
 
+// pad(base + r S) for r = 0..R-1 as pad(base) plus a compile-time offset
+// when S is a multiple of 8, or S = 1 with base a multiple of R and R
+// dividing 8 (then the LDS addresses of a butterfly share one register).
+template <int S, int R>
+__device__ __forceinline__ constexpr bool pad_splits() { return S % 8 == 0 || (S == 1 && R <= 8); }
+template <int S, int R>
+__device__ __forceinline__ constexpr int pad_step() { return S % 8 == 0 ? S + S / 8 : 1; }
+
 // The same stage with the length, radix and stride known at compile time
-// (power-of-two lengths): every index is a shift or a mask.
+// (power-of-two lengths): every index is a shift or a mask.  With the pencil
+// count PC known too and PC n/R a multiple of FT, every thread has exactly NB
+// butterflies and no bound is tested.  The twiddle of k = 0 is 1, whose
+// product is exact, so it is not skipped (no divergent branch).
 template <typename T, int N, int R, int NS, bool INV, int PC>
 __device__ __forceinline__ void stage_c(cpx<T>* a, int P, int ld, const cpx<T>* __restrict__ tw) {
     constexpr int NB = (FE + R - 1) / R;
     constexpr int nR = N / R, span = N / (NS * R);
+    constexpr bool EXACT = PC > 0 && PC * nR == NB * FT;
     const int nb = (PC > 0 ? PC : P) * nR;
     cpx<T> v[NB][R];
-    int dst[NB], pens[NB];
+    int dst[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int b = threadIdx.x + q * FT;
         dst[q] = -1;
-        if (b < nb) {
+        if (EXACT || b < nb) {
             const int pen = b / nR, j = b % nR;
             const int jq = j / NS, k = j % NS;
             const cpx<T>* src = a + pen * ld;
+            if constexpr (nR % 8 == 0) src += pad(j);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                cpx<T> x = src[pad(j + r * nR)];
-                if (NS > 1 && r > 0 && k > 0) {
+                cpx<T> x = nR % 8 == 0 ? src[r * (nR + nR / 8)] : src[pad(j + r * nR)];
+                if (NS > 1 && r > 0) {
                     cpx<T> w = tw[k * r * span];
                     if (INV) w.y = -w.y;
                     x = cmul<T>(x, w);
                 }
                 v[q][r] = x;
             }
-            dst[q] = jq * NS * R + k;
-            pens[q] = pen * ld;
+            dst[q] = pen * ld + (pad_splits<NS, R>() ? pad(jq * NS * R + k) : jq * NS * R + k);
         }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        if (dst[q] >= 0) {
+        if (EXACT || dst[q] >= 0) {
             dft_small<T, R, INV>(v[q]);
+            if constexpr (pad_splits<NS, R>()) {
+                cpx<T>* o = a + dst[q];
 #pragma unroll
-            for (int r = 0; r < R; ++r) a[pens[q] + pad(dst[q] + r * NS)] = v[q][r];
+                for (int r = 0; r < R; ++r) o[r * pad_step<NS, R>()] = v[q][r];
+            } else {
+                // dst = pen ld + m: the pencil base is ld times the quotient
+                const int pen = (threadIdx.x + q * FT) / nR, m = dst[q] - pen * ld;
+#pragma unroll
+                for (int r = 0; r < R; ++r) a[pen * ld + pad(m + r * NS)] = v[q][r];
+            }
         }
     }
     __syncthreads();
@@ -292,7 +312,9 @@ __device__ __forceinline__ void fft_any(cpx<T>* a, int n, int P, int ld, const c
 // Pass X (forward): charge assembly + two-for-one real FFT along x.
 // Work item: a pair of rows (y, y+1) at one z.  P pairs per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int NC>
+// FULL: every pair of the workgroup exists (no bound tests); with NC known the
+// P n elements also fill the XIT element slots of every thread exactly.
+template <typename T, int NC, bool FULL = false>
 __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int P_) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -308,28 +330,30 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int P_)
     // before the first LDS store (a loop that stores as it loads would wait
     // for each element's loads in turn)
     constexpr int XIT = FE / 2;
+    constexpr bool EXACT = NC > 0 && PC * NC == FT * XIT;
     long cr[XIT];
     T q0[XIT], q1[XIT];
 #pragma unroll
     for (int it = 0; it < XIT; ++it) {
         const int t = threadIdx.x + it * FT;
         cr[it] = -1;
-        if (t < P * n) {
+        if (EXACT || t < P * n) {
             const int pen = cdiv<NC>(t, dn), x = t - pen * n, pr = pair0 + pen;
-            if (pr < npairs) cr[it] = (long)(2 * pr) * n + x;  // row 2 pr = y + ny z with y even
+            if (FULL || pr < npairs) cr[it] = (long)(2 * pr) * n + x;  // row 2 pr = y + ny z with y even
         }
     }
     // the densities of every species (up to MAXS) requested in one round
     T d0[MAXS][XIT], d1[MAXS][XIT];
 #pragma unroll
     for (int it = 0; it < XIT; ++it) {
-        q0[it] = cr[it] >= 0 ? s.rhob[cr[it]] : (T)0;
-        q1[it] = cr[it] >= 0 ? s.rhob[cr[it] + n] : (T)0;
+        const bool ok = (EXACT && FULL) || cr[it] >= 0;
+        q0[it] = ok ? s.rhob[cr[it]] : (T)0;
+        q1[it] = ok ? s.rhob[cr[it] + n] : (T)0;
 #pragma unroll
         for (int k = 0; k < MAXS; ++k) {
             const T* rk = rho + (long)k * s.N;
-            d0[k][it] = (k < s.ns && cr[it] >= 0) ? rk[cr[it]] : (T)0;
-            d1[k][it] = (k < s.ns && cr[it] >= 0) ? rk[cr[it] + n] : (T)0;
+            d0[k][it] = (k < s.ns && ok) ? rk[cr[it]] : (T)0;
+            d1[k][it] = (k < s.ns && ok) ? rk[cr[it] + n] : (T)0;
         }
     }
 #pragma unroll
@@ -345,7 +369,7 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int P_)
 #pragma unroll
     for (int it = 0; it < XIT; ++it) {
         const int t = threadIdx.x + it * FT;
-        if (t < P * n) {
+        if (EXACT || t < P * n) {
             const int pen = cdiv<NC>(t, dn), x = t - pen * n;
             a[pen * ld + pad(x)] = mk<T>(q0[it], q1[it]);
         }
@@ -358,7 +382,7 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int P_)
     for (int t = threadIdx.x; t < P * nh; t += FT) {
         int pen = cdiv<NHC>(t, dnh), k = t - pen * nh;
         int pr = pair0 + pen;
-        if (pr >= npairs) continue;
+        if (!FULL && pr >= npairs) continue;
         cpx<T> A = r[pen * ld + pad(k)];
         cpx<T> B = r[pen * ld + pad(k == 0 ? 0 : n - k)];
         // Q1 = (A + conj B)/2, Q2 = (A - conj B)/(2i)
@@ -373,7 +397,7 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int P_)
 // ---------------------------------------------------------------------------
 // Pass X' (inverse): two half spectra -> one complex sequence -> two real rows.
 // ---------------------------------------------------------------------------
-template <typename T, int NC>
+template <typename T, int NC, bool FULL = false>
 __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int P_) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* a = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -387,14 +411,15 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int P_)
     const cpx<T>* tw = stage_twiddles<T>(a, P * ld, s.tw[0], n);
     // loads first, as in the forward pass (P n <= FT FE / 2)
     constexpr int XIT = FE / 2;
+    constexpr bool EXACT = NC > 0 && PC * NC == FT * XIT;
     cpx<T> q1[XIT], q2[XIT];
 #pragma unroll
     for (int it = 0; it < XIT; ++it) {
         const int t = threadIdx.x + it * FT;
         q1[it] = q2[it] = mk<T>(0, 0);
-        if (t < P * n) {
+        if (EXACT || t < P * n) {
             const int pen = cdiv<NC>(t, dn), k = t - pen * n, pr = pair0 + pen;
-            if (pr < npairs) {
+            if (FULL || pr < npairs) {
                 const long row = 2 * pr;
                 const int kk = k < nh ? k : n - k;
                 q1[it] = S[row * s.nxs + kk];
@@ -405,7 +430,7 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int P_)
 #pragma unroll
     for (int it = 0; it < XIT; ++it) {
         const int t = threadIdx.x + it * FT;
-        if (t < P * n) {
+        if (EXACT || t < P * n) {
             const int pen = cdiv<NC>(t, dn), k = t - pen * n;
             const cpx<T> a1 = q1[it], a2 = q2[it];
             // k < nh: q1 + i q2; otherwise conj(q1) + i conj(q2) of the mirrored column
@@ -417,10 +442,10 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int P_)
 #pragma unroll
     for (int it = 0; it < XIT; ++it) {
         const int t = threadIdx.x + it * FT;
-        if (t >= P * n) continue;
+        if (!EXACT && t >= P * n) continue;
         int pen = cdiv<NC>(t, dn), x = t - pen * n;
         int pr = pair0 + pen;
-        if (pr >= npairs) continue;
+        if (!FULL && pr >= npairs) continue;
         long c0 = (long)(2 * pr) * n + x;
         cpx<T> v = a[pen * ld + pad(x)];
         s.phi[c0] = v.x;
@@ -468,6 +493,40 @@ __device__ __forceinline__ void load_tile(cpx<T>* a, int ld, int TC, int n, cons
     }
 }
 
+// Full groups of compile-time width TCC and length NC: row r, column i of the
+// group at g[r rs + i].  Thread t takes column t mod TCC of rows t / TCC +
+// it FT / TCC, so every address is a per-thread base plus a multiple of a
+// uniform step (FT / TCC is a multiple of 8, so pad() splits as well).
+// (groups that cover the workgroup's threads a whole number of times)
+template <int TCC, int NC>
+constexpr bool tile_c_ok() {
+    return TCC > 0 && NC > 0 && FT % TCC == 0 && (FT / TCC) % 8 == 0 && (TCC * NC) % FT == 0;
+}
+template <typename T, int TCC, int NC>
+__device__ __forceinline__ void load_tile_c(cpx<T>* a, int ld, const cpx<T>* g, long rs) {
+    constexpr int RPI = FT / TCC, ITS = TCC * NC / FT;
+    static_assert(tile_c_ok<TCC, NC>(), "group shape");
+    const int r0 = threadIdx.x / TCC, i = threadIdx.x % TCC;
+    const cpx<T>* src = g + (long)r0 * rs + i;
+    cpx<T>* dst = a + i * ld + pad(r0);
+    const long step = (long)RPI * rs;
+    cpx<T> v[ITS];
+#pragma unroll
+    for (int it = 0; it < ITS; ++it) v[it] = src[it * step];
+#pragma unroll
+    for (int it = 0; it < ITS; ++it) dst[it * (RPI + RPI / 8)] = v[it];
+}
+template <typename T, int TCC, int NC>
+__device__ __forceinline__ void store_tile_c(const cpx<T>* a, int ld, cpx<T>* g, long rs) {
+    constexpr int RPI = FT / TCC, ITS = TCC * NC / FT;
+    const int r0 = threadIdx.x / TCC, i = threadIdx.x % TCC;
+    cpx<T>* out = g + (long)r0 * rs + i;
+    const cpx<T>* src = a + i * ld + pad(r0);
+    const long step = (long)RPI * rs;
+#pragma unroll
+    for (int it = 0; it < ITS; ++it) out[it * step] = src[it * (RPI + RPI / 8)];
+}
+
 // ---------------------------------------------------------------------------
 // Pass Y (forward or inverse): pencils along y, TX consecutive kx per group.
 // ---------------------------------------------------------------------------
@@ -485,15 +544,20 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int TX) {
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec) + (long)z * n * s.nxs;
     const FDiv dtc(TCC > 0 ? 1 : TC);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[1], n);
-    load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int y, int i) { return S[(long)y * s.nxs + kx0 + i]; });
+    if constexpr (tile_c_ok<TCC, NC>()) load_tile_c<T, TCC, NC>(a, ld, S + kx0, s.nxs);
+    else load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int y, int i) { return S[(long)y * s.nxs + kx0 + i]; });
     __syncthreads();
     fft_n<T, INV, NC, TCC>(a, n, TC, ld, tw);
+    if constexpr (tile_c_ok<TCC, NC>()) {
+        store_tile_c<T, TCC, NC>(a, ld, S + kx0, s.nxs);
+    } else {
 #pragma unroll
-    for (int it = 0; it < FE; ++it) {
-        const int t = threadIdx.x + it * FT;
-        if (t >= TC * n) break;
-        int y = cdiv<TCC>(t, dtc), i = t - y * TC;
-        S[(long)y * s.nxs + kx0 + i] = a[i * ld + pad(y)];
+        for (int it = 0; it < FE; ++it) {
+            const int t = threadIdx.x + it * FT;
+            if (t >= TC * n) break;
+            int y = cdiv<TCC>(t, dtc), i = t - y * TC;
+            S[(long)y * s.nxs + kx0 + i] = a[i * ld + pad(y)];
+        }
     }
 }
 
@@ -513,17 +577,21 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int T
     const long zstride = (long)ny * s.nxs;
     const FDiv dtc(TCC > 0 ? 1 : TC), dn(NC > 0 ? 1 : n);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[2], n);
-    load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int z, int i) { return S[z * zstride + (long)ky * s.nxs + kx0 + i]; });
+    cpx<T>* G = S + (long)ky * s.nxs + kx0;  // row z of the group at G + z zstride
+    if constexpr (tile_c_ok<TCC, NC>()) load_tile_c<T, TCC, NC>(a, ld, G, zstride);
+    else load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int z, int i) { return G[z * zstride + i]; });
     __syncthreads();
     fft_n<T, false, NC, TCC>(a, n, TC, ld, tw);
     const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
+    const T K2y = s.k2[1][ky];
 #pragma unroll
     for (int it = 0; it < FE; ++it) {
         const int t = threadIdx.x + it * FT;
         if (t >= TC * n) break;
+        // with NC known: column i = t / NC advances by FT / NC per step, kz is fixed
         int i = cdiv<NC>(t, dn), kz = t - i * n;
         int kx = kx0 + i;
-        T K2 = s.k2[0][kx] + s.k2[1][ky] + s.k2[2][kz];
+        T K2 = s.k2[0][kx] + K2y + s.k2[2][kz];
         // FP32: the hardware reciprocal (1 ulp) instead of a correctly rounded
         // division; FP64 divides
         T g;
@@ -535,12 +603,16 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int T
     }
     __syncthreads();
     fft_n<T, true, NC, TCC>(a, n, TC, ld, tw);
+    if constexpr (tile_c_ok<TCC, NC>()) {
+        store_tile_c<T, TCC, NC>(a, ld, G, zstride);
+    } else {
 #pragma unroll
-    for (int it = 0; it < FE; ++it) {
-        const int t = threadIdx.x + it * FT;
-        if (t >= TC * n) break;
-        int z = cdiv<TCC>(t, dtc), i = t - z * TC;
-        S[z * zstride + (long)ky * s.nxs + kx0 + i] = a[i * ld + pad(z)];
+        for (int it = 0; it < FE; ++it) {
+            const int t = threadIdx.x + it * FT;
+            if (t >= TC * n) break;
+            int z = cdiv<TCC>(t, dtc), i = t - z * TC;
+            G[z * zstride + i] = a[i * ld + pad(z)];
+        }
     }
 }
 
@@ -552,9 +624,13 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int T
 
 template <typename T>
 __device__ __forceinline__ void x_fwd_any(const Sim<T>& s, int b, int P) {
+    const bool full = (b + 1) * P <= s.ny * s.nz / 2;
     switch (s.nx) {
-#define EK_CASE(L) \
-    case L: fft_x_fwd_body<T, L>(s, b, P); return;
+#define EK_CASE(L)                                                      \
+    case L:                                                             \
+        if (full) fft_x_fwd_body<T, L, true>(s, b, P);                  \
+        else fft_x_fwd_body<T, L, false>(s, b, P);                      \
+        return;
         EK_FFT_LENGTHS(EK_CASE)
 #undef EK_CASE
         default: fft_x_fwd_body<T, 0>(s, b, P);
@@ -562,9 +638,13 @@ __device__ __forceinline__ void x_fwd_any(const Sim<T>& s, int b, int P) {
 }
 template <typename T>
 __device__ __forceinline__ void x_inv_any(const Sim<T>& s, int b, int P) {
+    const bool full = (b + 1) * P <= s.ny * s.nz / 2;
     switch (s.nx) {
-#define EK_CASE(L) \
-    case L: fft_x_inv_body<T, L>(s, b, P); return;
+#define EK_CASE(L)                                                      \
+    case L:                                                             \
+        if (full) fft_x_inv_body<T, L, true>(s, b, P);                  \
+        else fft_x_inv_body<T, L, false>(s, b, P);                      \
+        return;
         EK_FFT_LENGTHS(EK_CASE)
 #undef EK_CASE
         default: fft_x_inv_body<T, 0>(s, b, P);
