@@ -90,3 +90,13 @@ def compare(w, g, o, label=""):
     out.update({"particle_x": dx, "particle_v": dv, "particle_F": dF})
     say(label, {k: (f"{v:.3e}" if isinstance(v, float) else v) for k, v in out.items()})
     return out
+
+
+def snapshot(g, w: W.Workload) -> O.OracleSim:
+    """The GPU state at a step boundary, as the oracle takes it (populations,
+    densities, velocity, flags, owners, particles)."""
+    parts = g.particles()
+    spheres = [dict(x=p["x"], v=p["v"], w=p["omega"], F=p["F"], T=p["T"], R=s.R, Z=s.Z, M=s.M, mode=s.mode)
+               for p, s in zip(parts, w.spheres)]
+    return O.OracleSim.from_state(oracle_params(w), spheres, g.field("populations"), g.field("density"),
+                                  g.field("velocity"), g.field("flag"), g.field("owner"))

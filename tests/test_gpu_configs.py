@@ -13,9 +13,8 @@ arithmetic at full size; flags, owners and Psi must agree exactly."""
 import numpy as np
 import pytest
 
-from oracle import oracle as O
 from paper_1607_04572_amd import workloads as W
-from parity_util import compare, make_gpu, make_oracle, oracle_params, say
+from parity_util import compare, make_gpu, make_oracle, say, snapshot
 
 pytestmark = pytest.mark.gpu
 
@@ -32,15 +31,6 @@ def fp64_ok(e):
     for k in ("density", "phi", "velocity", "populations", "force", "rhob"):
         assert e[k] < 1e-9, k
     assert e["particle_v"] < 1e-9 and e["particle_F"] < 1e-8
-
-
-def snapshot(g, w):
-    """The GPU state at a step boundary, as the oracle takes it."""
-    parts = g.particles()
-    spheres = [dict(x=p["x"], v=p["v"], w=p["omega"], F=p["F"], T=p["T"], R=s.R, Z=s.Z, M=s.M, mode=s.mode)
-               for p, s in zip(parts, w.spheres)]
-    return O.OracleSim.from_state(oracle_params(w), spheres, g.field("populations"), g.field("density"),
-                                  g.field("velocity"), g.field("flag"), g.field("owner"))
 
 
 def resume_one_step(w, warm, ok):

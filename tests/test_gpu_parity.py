@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_1607_04572_amd import workloads as W
-from parity_util import compare, make_gpu, make_oracle, say
+from parity_util import compare, make_gpu, make_oracle, say, snapshot
 
 pytestmark = pytest.mark.gpu
 
@@ -129,19 +129,36 @@ def test_fp32_prescribed_sphere_500_steps():
 
 def test_fp32_free_sphere_velocity():
     """FP32 path, free sphere (velocity Verlet): particle velocity within 1e-4
-    of the FP64 oracle.  The FP32 trajectory drifts by ~1e-6 cells, which can
-    flip a sub-cell of Psi at a near-tie; the field bars apply while the
-    geometry is identical, the velocity bar always."""
+    of the FP64 oracle at every checkpoint.  The FP32 trajectory drifts from
+    the FP64 one by ~1e-6 cells over a few hundred steps; a discrete event (a
+    cell covered, a Psi leaf centre crossing the surface) can then happen one
+    step apart on the two sides, and the solute it moves stays displaced even
+    after the geometry agrees again.  So the field bars apply while the two
+    trajectories are within rounding (steps 1 and 50), and at step 200 one
+    oracle step resumed from the GPU state checks the arithmetic again."""
     w = W.Workload(name="fp32_free", shape=(32, 32, 32), precision="fp32", species=W.salt(0.3, 0.01),
                    lambda_B=0.7, E=(0.01, 0.0, 0.0), steps=200,
                    spheres=[W.Sphere(x=(16.0, 16.0, 16.0), R=5.0, Z=40.0, M=500.0)])
-
-    def check(e):
+    say("case", w.name, w.shape, w.precision)
+    o = make_oracle(w)
+    g = make_gpu(w)
+    g.prepare()
+    done = 0
+    for cp in (1, 50, 200):
+        g.step(cp - done)
+        o.run(cp - done)
+        done = cp
+        e = compare(w, g, o, f"step {cp}")
         assert e["particle_v"] < 1e-4
-        if e["psi"] == 0.0:
+        if cp <= 50:
             fp32_fields_ok(e)
-
-    run_parity(w, [1, 50, 200], check)
+    g.sync()
+    r = snapshot(g, w)
+    g.step(1)
+    r.step()
+    e = compare(w, g, r, "resumed +1")
+    fp32_fields_ok(e)
+    g.close()
 
 
 def test_gouy_chapman_slab_on_gpu():
