@@ -50,41 +50,51 @@ __device__ __forceinline__ int psi_cell_class(double lx, double ly, double lz, d
     return -1;
 }
 
+// Ordering of the LDS accesses of one wavefront (its LDS operations are
+// executed in order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Leaf-centre count of a cut cell by a group of 16 lanes (the four groups of
-// a wavefront count four cells at once): lane j of the group takes the leaf
-// columns (i, j), i = 0..15, of the 16 x 16 grid.  The count is an integer,
-// so the order of the partial sums does not matter.  Returns the group's total
-// in every lane of the group.
-__device__ __forceinline__ int group_leaf_count(double lx, double ly, double lz, double R2) {
+// a wavefront count four cells at once).  Lane j of the group takes the leaf
+// columns (i, j), i = 0..15, along z.  For a column with s = fl(cx^2 + cy^2),
+// leaf k counts iff fl(s + cz_k^2) <= R^2, which is monotone in cz_k^2
+// (rounding is monotone): with the 16 values cz_k^2 sorted (sz, in LDS), the
+// column's count is the number of sorted values that pass, found by a binary
+// search of 4 probes plus a test of the largest -- the same count as 16 tests,
+// in 5.  The count is an integer, so the order of the partial sums does not
+// matter.  Returns the group's total in every lane of the group.
+__device__ __forceinline__ int group_leaf_count(double lx, double ly, double lz, double R2, double* sz) {
 #pragma clang fp contract(off)
-    const int j = threadIdx.x & 15;
-    double cz2[16];
+    const int j = threadIdx.x & 15, g0 = threadIdx.x & 48;  // lane in the group, group's first lane
+    const double cz = lz + (double)(2 * j + 1) * 0.03125;
+    const double c2 = cz * cz;
+    int rank = 0;  // position of c2 among the group's 16 values (ties by index)
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        double cz = lz + (double)(2 * k + 1) * 0.03125;
-        cz2[k] = cz * cz;
+        const double o = __shfl(c2, g0 + k);
+        rank += (o < c2 || (o == c2 && k < j)) ? 1 : 0;
     }
-    double czmin = cz2[0], czmax = cz2[0];
-#pragma unroll
-    for (int k = 1; k < 16; ++k) {
-        czmin = cz2[k] < czmin ? cz2[k] : czmin;
-        czmax = cz2[k] > czmax ? cz2[k] : czmax;
-    }
+    sz[rank] = c2;
+    wave_lds_sync();
     const double cy = ly + (double)(2 * j + 1) * 0.03125;
     const double cy2 = cy * cy;
+    const double top = sz[15];
     int cnt = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        double cx = lx + (double)(2 * i + 1) * 0.03125;
-        double sxy = cx * cx + cy2;
-        if (sxy + czmin > R2) continue;       // no leaf of this column inside (monotone)
-        if (sxy + czmax <= R2) {              // every leaf of this column inside
-            cnt += 16;
-            continue;
-        }
+        const double cx = lx + (double)(2 * i + 1) * 0.03125;
+        const double sxy = cx * cx + cy2;
+        int c = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) cnt += (sxy + cz2[k] <= R2) ? 1 : 0;
+        for (int st = 8; st >= 1; st >>= 1) c += (sxy + sz[c + st - 1] <= R2) ? st : 0;
+        c += (sxy + top <= R2) ? 1 : 0;  // all 16 (the probes stop at 15)
+        cnt += c;
     }
+    wave_lds_sync();  // every lane has read sz before the group writes it again
 #pragma unroll
     for (int off = 8; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
     return cnt;
@@ -93,10 +103,12 @@ __device__ __forceinline__ int group_leaf_count(double lx, double ly, double lz,
 // Cooperative Psi count: every lane of the wavefront calls this together; a
 // lane with need == true receives the count of its cell (lx, ly, lz = cell
 // corner relative to the sphere centre).  Pending cells are taken four at a
-// time, one per 16-lane group.
+// time, one per 16-lane group.  Blocks of PT threads.
 __device__ __forceinline__ int wave_psi_resolve(bool need, double lx, double ly, double lz, double R2, int mine) {
+    __shared__ double psz[PT / 16][16];  // sorted leaf-layer squares of each group's cell
     unsigned long long mask = __ballot(need);
     const int lane = threadIdx.x & 63, g = lane >> 4;
+    double* sz = psz[threadIdx.x >> 4];
     while (mask) {
         int src[4];
 #pragma unroll
@@ -107,7 +119,7 @@ __device__ __forceinline__ int wave_psi_resolve(bool need, double lx, double ly,
         const int l = g == 0 ? src[0] : (g == 1 ? src[1] : (g == 2 ? src[2] : src[3]));
         const int ls = l < 0 ? lane : l;  // groups without a cell count their own (discarded)
         const double bx = __shfl(lx, ls), by = __shfl(ly, ls), bz = __shfl(lz, ls), br = __shfl(R2, ls);
-        const int c = group_leaf_count(bx, by, bz, br);
+        const int c = group_leaf_count(bx, by, bz, br, sz);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int cq = __shfl(c, 16 * q);
