@@ -202,23 +202,52 @@ struct EKShared {
     __device__ __forceinline__ bool wall(int slot, int i) const { return elem(slot, i, NS + 5) != (T)0; }
 };
 
-// Load one plane; returns whether it holds a boundary cell or a partial volume.
+// In-plane part x + nx y of the cell index of each window record this thread
+// loads (records t = threadIdx.x + r TXW TYW); it is the same for every plane.
+// Records up to one past the tile's last valid cell wrap periodically; those
+// beyond (tiles wider than a small domain) serve no valid cell and are clamped
+// into range.
+// (FP32 only: the FP64 fused kernel has no registers to spare for them and
+// recomputes the offsets per plane.)
 template <typename T, int NS, int TXW, int TYW>
-__device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, TXW, TYW>& sh, int slot, int x0,
-                                              int y0, int z, const T* __restrict__ rin) {
+struct PlaneMap {
     using SH = EKShared<T, NS, TXW, TYW>;
-    const int zz = wrap1(z, s.nz);  // z in [-1, nz]
-    bool dirty = false;
-    for (int t = threadIdx.x; t < SH::WPL; t += TXW * TYW) {
-        int i = t % SH::WX, j = t / SH::WX;
-        // Records up to one past the tile's last valid cell wrap periodically;
-        // those beyond (tiles wider than a small domain) serve no valid cell
-        // and are clamped into range.
+    static constexpr int NT = TXW * TYW, NR = (SH::WPL + NT - 1) / NT;
+    static constexpr bool KEEP = sizeof(T) == 4;
+    uint32_t cxy[KEEP ? NR : 1];
+    int x0, y0;
+    __device__ __forceinline__ static uint32_t offset(const Sim<T>& s, int x0, int y0, int t) {
+        const int i = t % SH::WX, j = t / SH::WX;
         int x = wrap1(x0 + i - 1, s.nx), y = wrap1(y0 + j - 1, s.ny);
         x = x < s.nx ? x : s.nx - 1;
         y = y < s.ny ? y : s.ny - 1;
-        const uint32_t c = cidx32(s, x, y, zz);
-        const T* __restrict__ ui = s.u[s.cur];
+        return (uint32_t)x + (uint32_t)s.nx * (uint32_t)y;
+    }
+    __device__ __forceinline__ PlaneMap(const Sim<T>& s, int x0_, int y0_) : x0(x0_), y0(y0_) {
+        if constexpr (KEEP) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) cxy[r] = offset(s, x0, y0, threadIdx.x + r * NT);
+        }
+    }
+    __device__ __forceinline__ uint32_t at(const Sim<T>& s, int r) const {
+        if constexpr (KEEP) return cxy[r];
+        else return offset(s, x0, y0, threadIdx.x + r * NT);
+    }
+};
+
+// Load one plane; returns whether it holds a boundary cell or a partial volume.
+template <typename T, int NS, int TXW, int TYW>
+__device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, TXW, TYW>& sh, int slot,
+                                              const PlaneMap<T, NS, TXW, TYW>& pm, int z,
+                                              const T* __restrict__ rin) {
+    using SH = EKShared<T, NS, TXW, TYW>;
+    using PM = PlaneMap<T, NS, TXW, TYW>;
+    const uint32_t zoff = (uint32_t)wrap1(z, s.nz) * ((uint32_t)s.nx * (uint32_t)s.ny);  // z in [-1, nz]
+    const T* __restrict__ ui = s.u[s.cur];
+    bool dirty = false;
+    auto one = [&](int rr) {
+        const int t = threadIdx.x + rr * PM::NT;
+        const uint32_t c = pm.at(s, rr) + zoff;
         RecEK<T, NS> r;
 #pragma unroll
         for (int k = 0; k < NS; ++k) r.v[k] = ld32(rin + (long)k * s.N, c);
@@ -235,6 +264,16 @@ __device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, T
         for (int k = NS + 6; k < RecEK<T, NS>::NV; ++k) r.v[k] = (T)0;
         sh.put(slot, t, r);
         dirty |= (psi != 0.0f) || (fl & F_CUR);
+    };
+    if constexpr (PM::KEEP) {
+#pragma unroll
+        for (int rr = 0; rr < PM::NR; ++rr)
+            if (threadIdx.x + rr * PM::NT < SH::WPL) one(rr);
+    } else {
+        // one record at a time (two in flight would not fit the FP64 budget)
+#pragma nounroll
+        for (int rr = 0; rr < PM::NR; ++rr)
+            if (threadIdx.x + rr * PM::NT < SH::WPL) one(rr);
     }
     return dirty;
 }
@@ -339,9 +378,10 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
         K.ref2hz[k] = (T)(0.5 * s.z[k]) * ((T)s.rho_ref[k] * (T)2);
     }
     const T half_kT = (T)(0.5 * s.kT);
+    const PlaneMap<T, NS, TXW, TYW> pm(s, x0, y0);
     {
-        bool d0 = ek_load_plane<T, NS, TXW, TYW>(s, sh, (zbeg + 2) % 3, x0, y0, zbeg - 1, rin);
-        bool d1 = ek_load_plane<T, NS, TXW, TYW>(s, sh, zbeg % 3, x0, y0, zbeg, rin);
+        bool d0 = ek_load_plane<T, NS, TXW, TYW>(s, sh, (zbeg + 2) % 3, pm, zbeg - 1, rin);
+        bool d1 = ek_load_plane<T, NS, TXW, TYW>(s, sh, zbeg % 3, pm, zbeg, rin);
         int a0 = __syncthreads_or(d0), a1 = __syncthreads_or(d1);
         if (threadIdx.x == 0) {
             sh.dirty[(zbeg + 2) % 3] = a0;
@@ -361,7 +401,7 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
         if constexpr (FUSE && PREFETCH) {
             if (valid && !wall) lb_pull(s, Nbr(x, y, z, s.nx, s.ny, s.nz), fi);
         }
-        bool dn = ek_load_plane<T, NS, TXW, TYW>(s, sh, sp, x0, y0, z + 1, rin);
+        bool dn = ek_load_plane<T, NS, TXW, TYW>(s, sh, sp, pm, z + 1, rin);
         int an = __syncthreads_or(dn);
         if (threadIdx.x == 0) sh.dirty[sp] = an;
         __syncthreads();
