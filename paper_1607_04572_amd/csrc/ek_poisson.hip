@@ -2,7 +2,9 @@
 // paper uses an FFT-based solver, Sec. III.C).
 //
 // The charge density q = sum_k z_k rho_k + rho_b is transformed with
-// hand-written mixed-radix (4, 2, 3) Stockham FFTs held in LDS, multiplied by
+// hand-written Stockham FFTs held in LDS (radix 8 with compile-time plans for
+// the power-of-two lengths 32-512, a run-time mixed-radix (4, 2, 3) plan for
+// the others), multiplied by
 // the Green's function of the 7-point Laplacian, 4 pi lambda_B / K^2 with
 // K^2 = sum_d (2 - 2 cos(2 pi k_d / n_d)) and the k = 0 mode set to zero
 // (neutralising background), and transformed back.  Five passes over HBM:
