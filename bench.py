@@ -165,8 +165,8 @@ def main():
                     help="also run the plain copy kernel on buffers of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU "
-              "path: the domain decomposition is a design note, not an implementation.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU "
+              "path: the domain decomposition is described, not implemented.", file=sys.stderr)
         sys.exit(2)
 
     from paper_1607_04572_amd import workloads as W
