@@ -911,6 +911,7 @@ struct ek_batch {
     int ns = 0;
     bool dirty = true;
     hipGraphExec_t graph = nullptr;
+    int graph_items[KK_N] = {};  // work items per kind the captured launches were sized for
     int err = EK_OK;
 };
 
@@ -1003,11 +1004,11 @@ int push_table(ek_batch* b) {
     return EK_OK;
 }
 
-void enqueue_batch_step(ek_batch* b) {
-    launch_batch_particles_pre(b->dtab, b->stream);
-    launch_batch_poisson(b->dtab, b->stream);
-    launch_batch_particle_forces(b->dtab, b->stream);
-    launch_batch_fields(b->dtab, b->ns, b->stream);
+void enqueue_batch_step(ek_batch* b, const int* items) {
+    launch_batch_particles_pre(b->dtab, items, b->stream);
+    launch_batch_poisson(b->dtab, items, b->stream);
+    launch_batch_particle_forces(b->dtab, items, b->stream);
+    launch_batch_fields(b->dtab, items, b->ns, b->stream);
     launch_batch_finish(b->dtab, b->stream);
     launch_batch_flip(b->dtab, b->stream);
 }
@@ -1117,14 +1118,28 @@ int ek_batch_step(ek_batch* b, int k) {
         int r = push_table(b);
         if (r) return r;
     }
+    // launches sized by work-item totals: capture again when the table's changed
+    int items[KK_N];
+    bool same = true;
+    for (int k = 0; k < KK_N; ++k) {
+        items[k] = b->h.start[k][b->h.nsims];
+        same = same && items[k] == b->graph_items[k];
+    }
+    if (b->graph && !same) {
+        // the totals change only in push_table, which leaves the stream idle
+        BCHK(b, hipStreamSynchronize(b->stream));
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
     if (!b->graph) {
         hipGraph_t g = nullptr;
         BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_batch_step(b);
+        enqueue_batch_step(b, items);
         BCHK(b, hipStreamEndCapture(b->stream, &g));
         hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         BCHK(b, e);
+        for (int kk = 0; kk < KK_N; ++kk) b->graph_items[kk] = items[kk];
     }
     for (int i = 0; i < k; ++i) BCHK(b, hipGraphLaunch(b->graph, b->stream));
     return EK_OK;

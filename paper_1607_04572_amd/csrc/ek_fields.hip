@@ -256,9 +256,9 @@ __device__ __forceinline__ bool ek_load_plane(const Sim<T>& s, EKShared<T, NS, T
         r.v[NS] = ld32(s.phi, c);
         r.v[NS + 1] = (T)psi;
         const T* uc = ui + vidx(0, c);
-        r.v[NS + 2] = uc[0];
-        r.v[NS + 3] = uc[FB];
-        r.v[NS + 4] = uc[2 * FB];
+        r.v[NS + 2] = gld(uc);
+        r.v[NS + 3] = gld(uc + FB);
+        r.v[NS + 4] = gld(uc + 2 * FB);
         r.v[NS + 5] = (fl & F_CUR) ? (T)1 : (T)0;
 #pragma unroll
         for (int k = NS + 6; k < RecEK<T, NS>::NV; ++k) r.v[k] = (T)0;
@@ -427,9 +427,9 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
                 st32_nt(rout + (long)k * s.N, c, out);
             }
             T* fc = s.fext + vidx(0, c);
-            __builtin_nontemporal_store(fe[0], fc);
-            __builtin_nontemporal_store(fe[1], fc + FB);
-            __builtin_nontemporal_store(fe[2], fc + 2 * FB);
+            gst_nt(fc, fe[0]);
+            gst_nt(fc + FB, fe[1]);
+            gst_nt(fc + 2 * FB, fe[2]);
             if constexpr (FUSE) {
                 if (wall) {
                     lb_wall(s, c);
@@ -495,13 +495,14 @@ void launch_fields(const Sim<T>& s, hipStream_t st, hipEvent_t mid) {
 // Batched EK and LB (FP32 tables), same split as the single-simulation path.
 // ---------------------------------------------------------------------------
 constexpr int BATCH_FIELD_BLOCKS = 2048;
+constexpr bool FLAT_EK = false;
 
 // Up to two species: four waves per SIMD (the batch loop's bookkeeping puts the
 // kernel at 134 VGPRs, three waves, otherwise; four waves with a few spilled
 // registers serve about 3.5 % more cells per second).
 template <int NS>
 __global__ __launch_bounds__(EKTile<float>::TXW* EKTile<float>::TYW)
-__attribute__((amdgpu_waves_per_eu(NS <= 2 ? 4 : 2))) void kb_ek(const BatchTable* tab) {
+__attribute__((amdgpu_waves_per_eu(NS <= 2 ? 4 : 2))) void kb_ek(const BatchTable* __restrict__ tab) {
     constexpr int TXW = EKTile<float>::TXW, TYW = EKTile<float>::TYW, ZC = EKTile<float>::ZC;
     batch_loop<KK_EK>(tab, [](const Sim<float>& s, int b) {
         const int gx = (s.nx + TXW - 1) / TXW, gy = (s.ny + TYW - 1) / TYW;
@@ -510,15 +511,15 @@ __attribute__((amdgpu_waves_per_eu(NS <= 2 ? 4 : 2))) void kb_ek(const BatchTabl
     });
 }
 
-void launch_batch_fields(const BatchTable* tab, int ns, hipStream_t st) {
+void launch_batch_fields(const BatchTable* tab, const int* items, int ns, hipStream_t st) {
     constexpr int NT = EKTile<float>::TXW * EKTile<float>::TYW;
     switch (ns) {
-        case 1: hipLaunchKernelGGL(kb_ek<1>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
-        case 2: hipLaunchKernelGGL(kb_ek<2>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
-        case 3: hipLaunchKernelGGL(kb_ek<3>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
-        default: hipLaunchKernelGGL(kb_ek<4>, dim3(BATCH_FIELD_BLOCKS), dim3(NT), 0, st, tab); break;
+        case 1: hipLaunchKernelGGL(kb_ek<1>, dim3(batch_grid(FLAT_EK, items[KK_EK], (const void*)kb_ek<1>, NT, 0, BATCH_FIELD_BLOCKS)), dim3(NT), 0, st, tab); break;
+        case 2: hipLaunchKernelGGL(kb_ek<2>, dim3(batch_grid(FLAT_EK, items[KK_EK], (const void*)kb_ek<2>, NT, 0, BATCH_FIELD_BLOCKS)), dim3(NT), 0, st, tab); break;
+        case 3: hipLaunchKernelGGL(kb_ek<3>, dim3(batch_grid(FLAT_EK, items[KK_EK], (const void*)kb_ek<3>, NT, 0, BATCH_FIELD_BLOCKS)), dim3(NT), 0, st, tab); break;
+        default: hipLaunchKernelGGL(kb_ek<4>, dim3(batch_grid(FLAT_EK, items[KK_EK], (const void*)kb_ek<4>, NT, 0, BATCH_FIELD_BLOCKS)), dim3(NT), 0, st, tab); break;
     }
-    if constexpr (!kFuseFields<float>) launch_batch_lb(tab, st);
+    if constexpr (!kFuseFields<float>) launch_batch_lb(tab, items, st);
 }
 
 template void launch_fields<float>(const Sim<float>&, hipStream_t, hipEvent_t);

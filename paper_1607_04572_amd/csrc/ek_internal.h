@@ -225,6 +225,28 @@ struct BatchTable {
     Sim<float> sims[MAX_SLOTS];
 };
 
+// Grid of a persistent batched kernel: as many workgroups as the current
+// device holds at once (every CU at the kernel's occupancy), so that all of
+// them are resident and each walks the same number of work items; `fallback`
+// if the occupancy query fails. A non-stream query, valid during capture.
+inline int resident_grid(const void* kernel, int threads, size_t lds, int fallback) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess || cus < 1 || per < 1)
+        return fallback;
+    return cus * per;
+}
+
+// Grid of a batched launch. Flat: one workgroup per work item (`items`, the
+// total over the table, which the host knows when it captures the launch),
+// scheduled by the hardware like the single-simulation kernels; otherwise
+// the resident persistent grid. The loop below covers every item either way.
+inline int batch_grid(bool flat, int items, const void* kernel, int threads, size_t lds, int fallback) {
+    if (flat) return items > 0 ? items : 1;
+    return resident_grid(kernel, threads, lds, fallback);
+}
+
 // Persistent loop over the workgroups of kernel kind KK: f(sim, local block).
 template <int KK, typename F>
 __device__ __forceinline__ void batch_loop(const BatchTable* tab, F&& f) {
@@ -241,6 +263,16 @@ __device__ __forceinline__ void batch_loop(const BatchTable* tab, F&& f) {
         __syncthreads();
     }
 }
+
+// Global-memory access through a device pointer. A pointer read from memory
+// (the batched kernels take every field pointer from a table) is flat to the
+// compiler, and a flat access also counts against the LDS wait counter: each
+// wait for an LDS result then also waits for every global load and store in
+// flight. Kernel-argument pointers are global already; the cast costs nothing.
+template <typename T> using gmem = __attribute__((address_space(1))) T;
+template <typename T> __device__ __forceinline__ T gld(const T* p) { return *(const gmem<T>*)p; }
+template <typename T> __device__ __forceinline__ void gst(T* p, T v) { *(gmem<T>*)p = v; }
+template <typename T> __device__ __forceinline__ void gst_nt(T* p, T v) { __builtin_nontemporal_store(v, (gmem<T>*)p); }
 
 // i mod n for -n <= i < 2n (one conditional correction, no division).
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -285,11 +317,12 @@ template <typename T> void launch_particle_forces(const Sim<T>& s, hipStream_t s
 // closing kick; and_move: also the next step's kick and drift (inside a chain of steps)
 template <typename T> void launch_finish(const Sim<T>& s, hipStream_t st, bool and_move = false);
 template <typename T> void launch_diagnostics(const Sim<T>& s, hipStream_t st, double* out);
-// batched step pieces (FP32 tables)
-void launch_batch_particles_pre(const BatchTable* tab, hipStream_t st);
-void launch_batch_poisson(const BatchTable* tab, hipStream_t st);
-void launch_batch_fields(const BatchTable* tab, int ns, hipStream_t st);
-void launch_batch_particle_forces(const BatchTable* tab, hipStream_t st);
+// batched step pieces (FP32 tables); items[k] = total work items of kind k
+// over the table (start[k][nsims] of the table the launches will read)
+void launch_batch_particles_pre(const BatchTable* tab, const int* items, hipStream_t st);
+void launch_batch_poisson(const BatchTable* tab, const int* items, hipStream_t st);
+void launch_batch_fields(const BatchTable* tab, const int* items, int ns, hipStream_t st);
+void launch_batch_particle_forces(const BatchTable* tab, const int* items, hipStream_t st);
 void launch_batch_finish(const BatchTable* tab, hipStream_t st);
 void launch_batch_flip(BatchTable* tab, hipStream_t st);
 void launch_copy16(void* dst, const void* src, long n16, hipStream_t st);

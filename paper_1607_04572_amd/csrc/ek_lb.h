@@ -31,11 +31,11 @@ __device__ __forceinline__ uint32_t cidx32(const Sim<T>& s, int x, int y, int z)
 }
 template <typename T>
 __device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t e) {
-    return *(const T*)((const char*)base + (uint32_t)(e * (uint32_t)sizeof(T)));
+    return gld((const T*)((const char*)base + (uint32_t)(e * (uint32_t)sizeof(T))));
 }
 template <typename T>
 __device__ __forceinline__ void st32_nt(T* __restrict__ base, uint32_t e, T v) {
-    __builtin_nontemporal_store(v, (T*)((char*)base + (uint32_t)(e * (uint32_t)sizeof(T))));
+    gst_nt((T*)((char*)base + (uint32_t)(e * (uint32_t)sizeof(T))), v);
 }
 
 // ---------------------------------------------------------------------------
@@ -86,7 +86,7 @@ __device__ __forceinline__ void lb_pull(const Sim<T>& s, const Nbr& nb, T (&fi)[
     const T* __restrict__ fs = s.f[s.cur];
     sfor<19>([&](auto I) {
         constexpr int i = I;
-        fi[i] = fs[fidx(i, nb.src32(i))];
+        fi[i] = gld(fs + fidx(i, nb.src32(i)));
     });
 }
 
@@ -120,7 +120,7 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
                     double vb[3] = {0.0, 0.0, 0.0};
                     uint16_t ow = ld32(s.owner, nb.src32(i));
                     if (ow != NO_OWNER) {
-                        const PState& q = s.parts[ow];
+                        const gmem<PState>& q = *(const gmem<PState>*)(s.parts + ow);
                         double r[3] = {min_image((double)bx + 0.5, q.x[0], (double)nx),
                                        min_image((double)by + 0.5, q.x[1], (double)ny),
                                        min_image((double)bz + 0.5, q.x[2], (double)nz)};
@@ -129,7 +129,7 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
                         vb[2] = q.v[2] + (q.w[0] * r[1] - q.w[1] * r[0]);
                     }
                     double cv = q19x(i) * vb[0] + q19y(i) * vb[1] + q19z(i) * vb[2];
-                    fi[i] = fs[fidx(q19opp(i), c)] + (T)(6.0 * q19w(i) * cv);
+                    fi[i] = gld(fs + fidx(q19opp(i), c)) + (T)(6.0 * q19w(i) * cv);
                 }
             }
         });
@@ -156,7 +156,7 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
     {  // rest population: even part only
         const T w = (T)q19w(0);
         const T feq_e = w * (rho - (T)1.5 * usq);
-        __builtin_nontemporal_store(fi[0] + le * (fi[0] - feq_e) + (T)4.5 * w * g2 * (-uf3), fc);
+        gst_nt(fc, fi[0] + le * (fi[0] - feq_e) + (T)4.5 * w * g2 * (-uf3));
     }
     // TRT per pair: the even part (symmetric relaxation and the even forcing
     // term) is shared by i and ibar, the odd part changes sign.
@@ -169,28 +169,28 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
         const T feq_e = w * (rho + (T)4.5 * cu * cu - (T)1.5 * usq);
         const T ev = le * ((T)0.5 * ps[i] - feq_e) + (T)4.5 * w * g2 * (cu * cf - uf3);
         const T od = lo * ((T)0.5 * pd[i] - (T)3 * w * cj) + (T)3 * w * cf;
-        __builtin_nontemporal_store(fi[i] + ev + od, fc + i * FB);
-        __builtin_nontemporal_store(fi[o] + ev - od, fc + o * FB);
+        gst_nt(fc + i * FB, fi[i] + ev + od);
+        gst_nt(fc + o * FB, fi[o] + ev - od);
     });
     T* uc = uo + vidx(0, c);
-    __builtin_nontemporal_store(ux, uc);
-    __builtin_nontemporal_store(uy, uc + FB);
-    __builtin_nontemporal_store(uz, uc + 2 * FB);
+    gst_nt(uc, ux);
+    gst_nt(uc + FB, uy);
+    gst_nt(uc + 2 * FB, uz);
 }
 
 // Velocity of a boundary cell (no populations are streamed there).
 template <typename T>
 __device__ __forceinline__ void lb_wall(const Sim<T>& s, uint32_t c) {
     T* __restrict__ uc = s.u[s.cur ^ 1] + vidx(0, c);
-    __builtin_nontemporal_store((T)0, uc);
-    __builtin_nontemporal_store((T)0, uc + FB);
-    __builtin_nontemporal_store((T)0, uc + 2 * FB);
+    gst_nt(uc, (T)0);
+    gst_nt(uc + FB, (T)0);
+    gst_nt(uc + 2 * FB, (T)0);
 }
 
 // Launch geometry of the stand-alone LB kernel: workgroup b covers cells
 // [256 (b mod nbp), 256 (b mod nbp) + 256) of plane z = b div nbp,
 // nbp = ceil(nx ny / 256) (the grid size is grids_of(...).n[KK_LB]).
 template <typename T> void launch_lb(const Sim<T>& s, hipStream_t st);
-void launch_batch_lb(const BatchTable* tab, hipStream_t st);
+void launch_batch_lb(const BatchTable* tab, const int* items, hipStream_t st);
 
 }  // namespace ek

@@ -23,7 +23,7 @@ __device__ __forceinline__ void lb_body(const Sim<T>& s, int bx_, int by_, int g
     lb_pull(s, nb, fi);
     const uint8_t fl = ld32(s.flag, c);
     const T* fc = s.fext + vidx(0, c);
-    const T fx = fc[0], fy = fc[FB], fz = fc[2 * FB];
+    const T fx = gld(fc), fy = gld(fc + FB), fz = gld(fc + 2 * FB);
     if (fl & F_CUR) {
         lb_wall(s, c);
         return;
@@ -43,13 +43,17 @@ void launch_lb(const Sim<T>& s, hipStream_t st) {
 }
 
 constexpr int BATCH_LB_BLOCKS = 2048;
+// One workgroup per 256-cell chunk: a persistent grid walking the chunks
+// streams about 20 % slower (601 against 494 us on one 256^3 box).
+constexpr bool FLAT_LB = true;
 
-__global__ __launch_bounds__(BT) void kb_lb(const BatchTable* tab) {
+__global__ __launch_bounds__(BT) void kb_lb(const BatchTable* __restrict__ tab) {
     batch_loop<KK_LB>(tab, [](const Sim<float>& s, int b) { lb_body<float, true>(s, b, 0, 0); });
 }
 
-void launch_batch_lb(const BatchTable* tab, hipStream_t st) {
-    hipLaunchKernelGGL(kb_lb, dim3(BATCH_LB_BLOCKS), dim3(BT), 0, st, tab);
+void launch_batch_lb(const BatchTable* tab, const int* items, hipStream_t st) {
+    const int grid = batch_grid(FLAT_LB, items[KK_LB], (const void*)kb_lb, BT, 0, BATCH_LB_BLOCKS);
+    hipLaunchKernelGGL(kb_lb, dim3(grid), dim3(BT), 0, st, tab);
 }
 
 template void launch_lb<float>(const Sim<float>&, hipStream_t);

@@ -1153,61 +1153,62 @@ void launch_finish(const Sim<T>& s, hipStream_t st, bool and_move) {
 // ---------------------------------------------------------------------------
 constexpr int BATCH_PART_BLOCKS = 1024;
 constexpr int BATCH_SMALL_BLOCKS = 256;
+constexpr bool FLAT_PART = false;
 
-__global__ void kb_move(const BatchTable* tab) {
+__global__ void kb_move(const BatchTable* __restrict__ tab) {
     batch_loop<KK_MOVE>(tab, [](const Sim<float>& s, int b) { move_body<float>(s, b, 0, 0, 0); });
 }
-__global__ __launch_bounds__(PT) void kb_geometry(const BatchTable* tab) {
+__global__ __launch_bounds__(PT) void kb_geometry(const BatchTable* __restrict__ tab) {
     batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
         geometry_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk, 0);
     });
 }
-__global__ __launch_bounds__(PT) void kb_boundary(const BatchTable* tab) {
+__global__ __launch_bounds__(PT) void kb_boundary(const BatchTable* __restrict__ tab) {
     batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
         boundary_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
-__global__ __launch_bounds__(PT) void kb_boundary_post(const BatchTable* tab) {
+__global__ __launch_bounds__(PT) void kb_boundary_post(const BatchTable* __restrict__ tab) {
     batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
         boundary_post_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
-__global__ __launch_bounds__(PT) void kb_pool(const BatchTable* tab) {
+__global__ __launch_bounds__(PT) void kb_pool(const BatchTable* __restrict__ tab) {
     batch_loop<KK_POOL>(tab, [](const Sim<float>& s, int b) { pool_body<float>(s, b, 0, POOL_BLOCKS); });
 }
-__global__ __launch_bounds__(PT) void kb_refill_vacated(const BatchTable* tab) {
+__global__ __launch_bounds__(PT) void kb_refill_vacated(const BatchTable* __restrict__ tab) {
     batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
         if (!s.pv) refill_vacated_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
-__global__ __launch_bounds__(PT) void kb_refill_stable(const BatchTable* tab) {
+__global__ __launch_bounds__(PT) void kb_refill_stable(const BatchTable* __restrict__ tab) {
     batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
         if (!s.pv) refill_stable_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
-__global__ __launch_bounds__(PT) void kb_particle_forces(const BatchTable* tab) {
+__global__ __launch_bounds__(PT) void kb_particle_forces(const BatchTable* __restrict__ tab) {
     batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
         hydro_force_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
         el_force_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
-__global__ void kb_finish(const BatchTable* tab) {
+__global__ void kb_finish(const BatchTable* __restrict__ tab) {
     batch_loop<KK_PRED>(tab, [](const Sim<float>& s, int b) { finish_body<float>(s, b, 0, 0); });
 }
 
-void launch_batch_particles_pre(const BatchTable* tab, hipStream_t st) {
+void launch_batch_particles_pre(const BatchTable* tab, const int* items, hipStream_t st) {
     hipLaunchKernelGGL(kb_move, dim3(BATCH_SMALL_BLOCKS), dim3(64), 0, st, tab);
-    hipLaunchKernelGGL(kb_geometry, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
-    hipLaunchKernelGGL(kb_boundary, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
-    hipLaunchKernelGGL(kb_boundary_post, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
-    hipLaunchKernelGGL(kb_pool, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
-    hipLaunchKernelGGL(kb_refill_vacated, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
-    hipLaunchKernelGGL(kb_refill_stable, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_geometry, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_geometry, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_boundary, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_boundary, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_boundary_post, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_boundary_post, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_pool, dim3(batch_grid(FLAT_PART, items[KK_POOL], (const void*)kb_pool, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_refill_vacated, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_refill_vacated, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
+    hipLaunchKernelGGL(kb_refill_stable, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_refill_stable, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
 }
 
 // after the Poisson solve and before the field update (see k_particle_forces)
-void launch_batch_particle_forces(const BatchTable* tab, hipStream_t st) {
-    hipLaunchKernelGGL(kb_particle_forces, dim3(BATCH_PART_BLOCKS), dim3(PT), 0, st, tab);
+void launch_batch_particle_forces(const BatchTable* tab, const int* items, hipStream_t st) {
+    hipLaunchKernelGGL(kb_particle_forces, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_particle_forces, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
 }
 
 void launch_batch_finish(const BatchTable* tab, hipStream_t st) {

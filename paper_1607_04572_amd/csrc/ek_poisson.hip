@@ -59,6 +59,27 @@ __device__ __forceinline__ cpx<T> mk(T x, T y) {
     return r;
 }
 
+// Complex elements to and from global memory as native two-element vectors
+// (the HIP vector types are classes that do not copy across address spaces).
+template <typename T>
+__device__ __forceinline__ cpx<T> gld_c(const cpx<T>* p) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(const gmem<v2>*)p;
+    return mk<T>(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void gst_c(cpx<T>* p, cpx<T> v) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *(gmem<v2>*)p = w;
+}
+__device__ __forceinline__ float2 gld(const float2* p) { return gld_c<float>(p); }
+__device__ __forceinline__ double2 gld(const double2* p) { return gld_c<double>(p); }
+__device__ __forceinline__ void gst(float2* p, float2 v) { gst_c<float>(p, v); }
+__device__ __forceinline__ void gst(double2* p, double2 v) { gst_c<double>(p, v); }
+
 // Radix-R DFT of v[0..R) in registers (forward: e^{-2 pi i qm/R}).
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft_small(cpx<T> (&v)[R]) {
@@ -273,7 +294,7 @@ template <typename T>
 __device__ __forceinline__ const cpx<T>* stage_twiddles(cpx<T>* a, int data_elems, const T* tw, int n) {
     cpx<T>* t = a + data_elems;
     const cpx<T>* g = reinterpret_cast<const cpx<T>*>(tw);
-    for (int m = threadIdx.x; m < n; m += FT) t[m] = g[m];
+    for (int m = threadIdx.x; m < n; m += FT) t[m] = gld(g + m);
     return t;
 }
 
@@ -349,13 +370,13 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int P_)
 #pragma unroll
     for (int it = 0; it < XIT; ++it) {
         const bool ok = (EXACT && FULL) || cr[it] >= 0;
-        q0[it] = ok ? s.rhob[cr[it]] : (T)0;
-        q1[it] = ok ? s.rhob[cr[it] + n] : (T)0;
+        q0[it] = ok ? gld(s.rhob + cr[it]) : (T)0;
+        q1[it] = ok ? gld(s.rhob + cr[it] + n) : (T)0;
 #pragma unroll
         for (int k = 0; k < MAXS; ++k) {
             const T* rk = rho + (long)k * s.N;
-            d0[k][it] = (k < s.ns && ok) ? rk[cr[it]] : (T)0;
-            d1[k][it] = (k < s.ns && ok) ? rk[cr[it] + n] : (T)0;
+            d0[k][it] = (k < s.ns && ok) ? gld(rk + cr[it]) : (T)0;
+            d1[k][it] = (k < s.ns && ok) ? gld(rk + cr[it] + n) : (T)0;
         }
     }
 #pragma unroll
@@ -391,8 +412,8 @@ __device__ __forceinline__ void fft_x_fwd_body(const Sim<T>& s, int bx_, int P_)
         cpx<T> q1 = mk<T>((T)0.5 * (A.x + B.x), (T)0.5 * (A.y - B.y));
         cpx<T> q2 = mk<T>((T)0.5 * (A.y + B.y), (T)-0.5 * (A.x - B.x));
         long row = 2 * pr;
-        S[row * s.nxs + k] = q1;
-        S[(row + 1) * s.nxs + k] = q2;
+        gst(S + row * s.nxs + k, q1);
+        gst(S + (row + 1) * s.nxs + k, q2);
     }
 }
 
@@ -424,8 +445,8 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int P_)
             if (FULL || pr < npairs) {
                 const long row = 2 * pr;
                 const int kk = k < nh ? k : n - k;
-                q1[it] = S[row * s.nxs + kk];
-                q2[it] = S[(row + 1) * s.nxs + kk];
+                q1[it] = gld(S + row * s.nxs + kk);
+                q2[it] = gld(S + (row + 1) * s.nxs + kk);
             }
         }
     }
@@ -450,8 +471,8 @@ __device__ __forceinline__ void fft_x_inv_body(const Sim<T>& s, int bx_, int P_)
         if (!FULL && pr >= npairs) continue;
         long c0 = (long)(2 * pr) * n + x;
         cpx<T> v = a[pen * ld + pad(x)];
-        s.phi[c0] = v.x;
-        s.phi[c0 + n] = v.y;
+        gst(s.phi + c0, v.x);
+        gst(s.phi + c0 + n, v.y);
     }
 }
 
@@ -514,7 +535,7 @@ __device__ __forceinline__ void load_tile_c(cpx<T>* a, int ld, const cpx<T>* g, 
     const long step = (long)RPI * rs;
     cpx<T> v[ITS];
 #pragma unroll
-    for (int it = 0; it < ITS; ++it) v[it] = src[it * step];
+    for (int it = 0; it < ITS; ++it) v[it] = gld(src + it * step);
 #pragma unroll
     for (int it = 0; it < ITS; ++it) dst[it * (RPI + RPI / 8)] = v[it];
 }
@@ -526,7 +547,7 @@ __device__ __forceinline__ void store_tile_c(const cpx<T>* a, int ld, cpx<T>* g,
     const cpx<T>* src = a + i * ld + pad(r0);
     const long step = (long)RPI * rs;
 #pragma unroll
-    for (int it = 0; it < ITS; ++it) out[it * step] = src[it * (RPI + RPI / 8)];
+    for (int it = 0; it < ITS; ++it) gst(out + it * step, src[it * (RPI + RPI / 8)]);
 }
 
 // ---------------------------------------------------------------------------
@@ -547,7 +568,7 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int TX) {
     const FDiv dtc(TCC > 0 ? 1 : TC);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[1], n);
     if constexpr (tile_c_ok<TCC, NC>()) load_tile_c<T, TCC, NC>(a, ld, S + kx0, s.nxs);
-    else load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int y, int i) { return S[(long)y * s.nxs + kx0 + i]; });
+    else load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int y, int i) { return gld(S + (long)y * s.nxs + kx0 + i); });
     __syncthreads();
     fft_n<T, INV, NC, TCC>(a, n, TC, ld, tw);
     if constexpr (tile_c_ok<TCC, NC>()) {
@@ -558,7 +579,7 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int TX) {
             const int t = threadIdx.x + it * FT;
             if (t >= TC * n) break;
             int y = cdiv<TCC>(t, dtc), i = t - y * TC;
-            S[(long)y * s.nxs + kx0 + i] = a[i * ld + pad(y)];
+            gst(S + (long)y * s.nxs + kx0 + i, a[i * ld + pad(y)]);
         }
     }
 }
@@ -581,11 +602,11 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int T
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[2], n);
     cpx<T>* G = S + (long)ky * s.nxs + kx0;  // row z of the group at G + z zstride
     if constexpr (tile_c_ok<TCC, NC>()) load_tile_c<T, TCC, NC>(a, ld, G, zstride);
-    else load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int z, int i) { return G[z * zstride + i]; });
+    else load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int z, int i) { return gld(G + z * zstride + i); });
     __syncthreads();
     fft_n<T, false, NC, TCC>(a, n, TC, ld, tw);
     const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
-    const T K2y = s.k2[1][ky];
+    const T K2y = gld(s.k2[1] + ky);
 #pragma unroll
     for (int it = 0; it < FE; ++it) {
         const int t = threadIdx.x + it * FT;
@@ -593,7 +614,7 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int T
         // with NC known: column i = t / NC advances by FT / NC per step, kz is fixed
         int i = cdiv<NC>(t, dn), kz = t - i * n;
         int kx = kx0 + i;
-        T K2 = s.k2[0][kx] + K2y + s.k2[2][kz];
+        T K2 = gld(s.k2[0] + kx) + K2y + gld(s.k2[2] + kz);
         // FP32: the hardware reciprocal (1 ulp) instead of a correctly rounded
         // division; FP64 divides
         T g;
@@ -613,7 +634,7 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int T
             const int t = threadIdx.x + it * FT;
             if (t >= TC * n) break;
             int z = cdiv<TCC>(t, dtc), i = t - z * TC;
-            G[z * zstride + i] = a[i * ld + pad(z)];
+            gst(G + z * zstride + i, a[i * ld + pad(z)]);
         }
     }
 }
@@ -728,6 +749,7 @@ void launch_charge_poisson(const Sim<T>& s, hipStream_t st) {
 // size is the largest any allowed edge needs.
 // ---------------------------------------------------------------------------
 constexpr int BATCH_FFT_BLOCKS = 2048;
+constexpr bool FLAT_FFT = false;
 
 static size_t batch_lds_x() {
     size_t m = 0;
@@ -748,27 +770,27 @@ static size_t batch_lds_yz() {
 
 // (run-time bodies only: the length dispatch inside the batch loop costs
 // registers and spills)
-__global__ __launch_bounds__(FT) void kb_fft_x_fwd(const BatchTable* tab) {
+__global__ __launch_bounds__(FT) void kb_fft_x_fwd(const BatchTable* __restrict__ tab) {
     batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) { fft_x_fwd_body<float, 0>(s, b, fft_pencils_x(s.nx)); });
 }
-__global__ __launch_bounds__(FT) void kb_fft_x_inv(const BatchTable* tab) {
+__global__ __launch_bounds__(FT) void kb_fft_x_inv(const BatchTable* __restrict__ tab) {
     batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) { fft_x_inv_body<float, 0>(s, b, fft_pencils_x(s.nx)); });
 }
 template <bool INV>
-__global__ __launch_bounds__(FT) void kb_fft_y(const BatchTable* tab) {
+__global__ __launch_bounds__(FT) void kb_fft_y(const BatchTable* __restrict__ tab) {
     batch_loop<KK_FFTY>(tab, [](const Sim<float>& s, int b) { fft_y_body<float, INV, 0, 0>(s, b, fft_tile_kx(s.ny, 4)); });
 }
-__global__ __launch_bounds__(FT) void kb_fft_z_green(const BatchTable* tab) {
+__global__ __launch_bounds__(FT) void kb_fft_z_green(const BatchTable* __restrict__ tab) {
     batch_loop<KK_FFTZ>(tab, [](const Sim<float>& s, int b) { fft_z_green_body<float, 0, 0>(s, b, fft_tile_kx(s.nz, 4)); });
 }
 
-void launch_batch_poisson(const BatchTable* tab, hipStream_t st) {
+void launch_batch_poisson(const BatchTable* tab, const int* items, hipStream_t st) {
     size_t lx = batch_lds_x(), lyz = batch_lds_yz();
-    hipLaunchKernelGGL(kb_fft_x_fwd, dim3(BATCH_FFT_BLOCKS), dim3(FT), lx, st, tab);
-    hipLaunchKernelGGL(kb_fft_y<false>, dim3(BATCH_FFT_BLOCKS), dim3(FT), lyz, st, tab);
-    hipLaunchKernelGGL(kb_fft_z_green, dim3(BATCH_FFT_BLOCKS), dim3(FT), lyz, st, tab);
-    hipLaunchKernelGGL(kb_fft_y<true>, dim3(BATCH_FFT_BLOCKS), dim3(FT), lyz, st, tab);
-    hipLaunchKernelGGL(kb_fft_x_inv, dim3(BATCH_FFT_BLOCKS), dim3(FT), lx, st, tab);
+    hipLaunchKernelGGL(kb_fft_x_fwd, dim3(batch_grid(FLAT_FFT, items[KK_FFTX], (const void*)kb_fft_x_fwd, FT, lx, BATCH_FFT_BLOCKS)), dim3(FT), lx, st, tab);
+    hipLaunchKernelGGL(kb_fft_y<false>, dim3(batch_grid(FLAT_FFT, items[KK_FFTY], (const void*)kb_fft_y<false>, FT, lyz, BATCH_FFT_BLOCKS)), dim3(FT), lyz, st, tab);
+    hipLaunchKernelGGL(kb_fft_z_green, dim3(batch_grid(FLAT_FFT, items[KK_FFTZ], (const void*)kb_fft_z_green, FT, lyz, BATCH_FFT_BLOCKS)), dim3(FT), lyz, st, tab);
+    hipLaunchKernelGGL(kb_fft_y<true>, dim3(batch_grid(FLAT_FFT, items[KK_FFTY], (const void*)kb_fft_y<true>, FT, lyz, BATCH_FFT_BLOCKS)), dim3(FT), lyz, st, tab);
+    hipLaunchKernelGGL(kb_fft_x_inv, dim3(batch_grid(FLAT_FFT, items[KK_FFTX], (const void*)kb_fft_x_inv, FT, lx, BATCH_FFT_BLOCKS)), dim3(FT), lx, st, tab);
 }
 
 template void launch_charge_poisson<float>(const Sim<float>&, hipStream_t);
