@@ -504,7 +504,7 @@ template <int NS>
 __global__ __launch_bounds__(EKTile<float>::TXW* EKTile<float>::TYW)
 __attribute__((amdgpu_waves_per_eu(NS <= 2 ? 4 : 2))) void kb_ek(const BatchTable* __restrict__ tab) {
     constexpr int TXW = EKTile<float>::TXW, TYW = EKTile<float>::TYW, ZC = EKTile<float>::ZC;
-    batch_loop<KK_EK>(tab, [](const Sim<float>& s, int b) {
+    batch_run<KK_EK, FLAT_EK>(tab, [](const Sim<float>& s, int b) {
         const int gx = (s.nx + TXW - 1) / TXW, gy = (s.ny + TYW - 1) / TYW;
         const int nt = gx * gy * ((s.nz + ZC - 1) / ZC);
         ek_body<float, true, NS, TXW, TYW, kFuseFields<float>, kPrefetch<float>>(s, b, 0, 0, ZC, gx, gy, nt);

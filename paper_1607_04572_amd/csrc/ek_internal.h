@@ -239,29 +239,57 @@ inline int resident_grid(const void* kernel, int threads, size_t lds, int fallba
 }
 
 // Grid of a batched launch. Flat: one workgroup per work item (`items`, the
-// total over the table, which the host knows when it captures the launch),
-// scheduled by the hardware like the single-simulation kernels; otherwise
-// the resident persistent grid. The loop below covers every item either way.
+// total over the table, which the host knows when it captures the launch,
+// and captures again when it changes), scheduled by the hardware like the
+// single-simulation kernels; otherwise the resident persistent grid.
 inline int batch_grid(bool flat, int items, const void* kernel, int threads, size_t lds, int fallback) {
     if (flat) return items > 0 ? items : 1;
     return resident_grid(kernel, threads, lds, fallback);
 }
 
+// Slot of work item w of kind KK: the last slot whose prefix sum is <= w.
+template <int KK>
+__device__ __forceinline__ int batch_slot(const BatchTable* tab, int n, int w) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (tab->start[KK][mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One work item per workgroup (flat launches: the grid is the table's total).
+// No loop: a loop around the body lets the compiler keep values of every
+// inlined length specialisation live across iterations (the batched FFT
+// passes took 170-255 VGPRs that way, 42-70 without it).
+template <int KK, typename F>
+__device__ __forceinline__ void batch_one(const BatchTable* tab, F&& f) {
+    const int n = tab->nsims;
+    const int w = blockIdx.x;
+    if (w >= tab->start[KK][n]) return;
+    const int lo = batch_slot<KK>(tab, n, w);
+    if (tab->active[lo]) f(tab->sims[lo], w - tab->start[KK][lo]);
+}
+
 // Persistent loop over the workgroups of kernel kind KK: f(sim, local block).
+// (The launch grid and the form of the kernel must agree: batch_run picks
+// both from one flag.)
 template <int KK, typename F>
 __device__ __forceinline__ void batch_loop(const BatchTable* tab, F&& f) {
     const int n = tab->nsims;
     const int total = tab->start[KK][n];
     for (int w = blockIdx.x; w < total; w += gridDim.x) {
-        int lo = 0, hi = n;
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (tab->start[KK][mid] <= w) lo = mid;
-            else hi = mid;
-        }
+        const int lo = batch_slot<KK>(tab, n, w);
         if (tab->active[lo]) f(tab->sims[lo], w - tab->start[KK][lo]);
         __syncthreads();
     }
+}
+
+template <int KK, bool FLAT, typename F>
+__device__ __forceinline__ void batch_run(const BatchTable* tab, F&& f) {
+    if constexpr (FLAT) batch_one<KK>(tab, f);
+    else batch_loop<KK>(tab, f);
 }
 
 // Global-memory access through a device pointer. A pointer read from memory

@@ -48,7 +48,7 @@ constexpr int BATCH_LB_BLOCKS = 2048;
 constexpr bool FLAT_LB = true;
 
 __global__ __launch_bounds__(BT) void kb_lb(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_LB>(tab, [](const Sim<float>& s, int b) { lb_body<float, true>(s, b, 0, 0); });
+    batch_run<KK_LB, FLAT_LB>(tab, [](const Sim<float>& s, int b) { lb_body<float, true>(s, b, 0, 0); });
 }
 
 void launch_batch_lb(const BatchTable* tab, const int* items, hipStream_t st) {

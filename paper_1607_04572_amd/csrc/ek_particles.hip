@@ -1153,41 +1153,41 @@ void launch_finish(const Sim<T>& s, hipStream_t st, bool and_move) {
 // ---------------------------------------------------------------------------
 constexpr int BATCH_PART_BLOCKS = 1024;
 constexpr int BATCH_SMALL_BLOCKS = 256;
-constexpr bool FLAT_PART = false;
+constexpr bool FLAT_PART = true;
 
 __global__ void kb_move(const BatchTable* __restrict__ tab) {
     batch_loop<KK_MOVE>(tab, [](const Sim<float>& s, int b) { move_body<float>(s, b, 0, 0, 0); });
 }
 __global__ __launch_bounds__(PT) void kb_geometry(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+    batch_run<KK_PART, FLAT_PART>(tab, [](const Sim<float>& s, int b) {
         geometry_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk, 0);
     });
 }
 __global__ __launch_bounds__(PT) void kb_boundary(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+    batch_run<KK_PART, FLAT_PART>(tab, [](const Sim<float>& s, int b) {
         boundary_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
 __global__ __launch_bounds__(PT) void kb_boundary_post(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+    batch_run<KK_PART, FLAT_PART>(tab, [](const Sim<float>& s, int b) {
         boundary_post_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
 __global__ __launch_bounds__(PT) void kb_pool(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_POOL>(tab, [](const Sim<float>& s, int b) { pool_body<float>(s, b, 0, POOL_BLOCKS); });
+    batch_run<KK_POOL, FLAT_PART>(tab, [](const Sim<float>& s, int b) { pool_body<float>(s, b, 0, POOL_BLOCKS); });
 }
 __global__ __launch_bounds__(PT) void kb_refill_vacated(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+    batch_run<KK_PART, FLAT_PART>(tab, [](const Sim<float>& s, int b) {
         if (!s.pv) refill_vacated_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
 __global__ __launch_bounds__(PT) void kb_refill_stable(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+    batch_run<KK_PART, FLAT_PART>(tab, [](const Sim<float>& s, int b) {
         if (!s.pv) refill_stable_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });
 }
 __global__ __launch_bounds__(PT) void kb_particle_forces(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_PART>(tab, [](const Sim<float>& s, int b) {
+    batch_run<KK_PART, FLAT_PART>(tab, [](const Sim<float>& s, int b) {
         hydro_force_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
         el_force_body<float>(s, b % s.nchunk, b / s.nchunk, s.nchunk);
     });

@@ -749,7 +749,7 @@ void launch_charge_poisson(const Sim<T>& s, hipStream_t st) {
 // size is the largest any allowed edge needs.
 // ---------------------------------------------------------------------------
 constexpr int BATCH_FFT_BLOCKS = 2048;
-constexpr bool FLAT_FFT = false;
+constexpr bool FLAT_FFT = true;
 
 static size_t batch_lds_x() {
     size_t m = 0;
@@ -768,20 +768,20 @@ static size_t batch_lds_yz() {
     return m;
 }
 
-// (run-time bodies only: the length dispatch inside the batch loop costs
-// registers and spills)
+// Flat launches with the same length dispatch as the single-simulation
+// passes (compile-time bodies for the powers of two).
 __global__ __launch_bounds__(FT) void kb_fft_x_fwd(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) { fft_x_fwd_body<float, 0>(s, b, fft_pencils_x(s.nx)); });
+    batch_run<KK_FFTX, FLAT_FFT>(tab, [](const Sim<float>& s, int b) { x_fwd_any<float>(s, b, fft_pencils_x(s.nx)); });
 }
 __global__ __launch_bounds__(FT) void kb_fft_x_inv(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_FFTX>(tab, [](const Sim<float>& s, int b) { fft_x_inv_body<float, 0>(s, b, fft_pencils_x(s.nx)); });
+    batch_run<KK_FFTX, FLAT_FFT>(tab, [](const Sim<float>& s, int b) { x_inv_any<float>(s, b, fft_pencils_x(s.nx)); });
 }
 template <bool INV>
 __global__ __launch_bounds__(FT) void kb_fft_y(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_FFTY>(tab, [](const Sim<float>& s, int b) { fft_y_body<float, INV, 0, 0>(s, b, fft_tile_kx(s.ny, 4)); });
+    batch_run<KK_FFTY, FLAT_FFT>(tab, [](const Sim<float>& s, int b) { y_any<float, INV>(s, b, fft_tile_kx(s.ny, 4)); });
 }
 __global__ __launch_bounds__(FT) void kb_fft_z_green(const BatchTable* __restrict__ tab) {
-    batch_loop<KK_FFTZ>(tab, [](const Sim<float>& s, int b) { fft_z_green_body<float, 0, 0>(s, b, fft_tile_kx(s.nz, 4)); });
+    batch_run<KK_FFTZ, FLAT_FFT>(tab, [](const Sim<float>& s, int b) { z_any<float>(s, b, fft_tile_kx(s.nz, 4)); });
 }
 
 void launch_batch_poisson(const BatchTable* tab, const int* items, hipStream_t st) {
