@@ -169,6 +169,16 @@ int ek_set_static_boundary(ek_ctx* c, const uint8_t* mask, const double* charge)
  * emptied and, in the partial-volume scheme, fluid cells keep (1 - Psi) of it. */
 int ek_set_fields(ek_ctx* c, int field, const void* host, size_t bytes);
 
+/* Seeded initial concentration computed on the device, no host buffer: the
+ * workloads' input recipe (not a step of the method), rho_k(cell) =
+ * mean_density_k (1 + noise (2U - 1)) with U = (splitmix64(cell ^ seed ^
+ * (k << 40)) >> 11) 2^-53 (splitmix64 of Steele, Lea and Flood, 2014; cells x
+ * fastest, k the species index), every operation rounded once in FP64 in that
+ * order.  The result is what ek_set_fields(DENSITY) stores for the same values
+ * computed on the host, and is treated as that call's is.  Errors:
+ * INVALID_ARG (noise not finite or |noise| > 1), DEVICE. */
+int ek_seed_density(ek_ctx* c, uint64_t seed, double noise);
+
 /* Compute the initial coverage (flags, Psi, particle charge) and apply the
  * initial-density rule.  Called by the first ek_step if not called before. */
 int ek_prepare(ek_ctx* c);
@@ -250,6 +260,12 @@ int ek_batch_create(size_t arena_bytes, int n_species, void* stream, void* arena
  * Synchronises the batch stream. */
 int ek_batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
                    const double* initial_density, long long n_steps, int* slot);
+
+/* ek_batch_admit with the seeded initial density of ek_seed_density(seed,
+ * noise) in place of a host array: the request's initial state is built on
+ * the device.  Errors as ek_batch_admit and ek_seed_density. */
+int ek_batch_admit_seeded(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
+                          uint64_t seed, double noise, long long n_steps, int* slot);
 
 /* Enqueue k batched steps; slots that reach their requested steps stop. */
 int ek_batch_step(ek_batch* b, int k);

@@ -574,6 +574,19 @@ int diagnostics(ek_ctx* c, Sim<T>& s, ek_diag* out) {
 
 }  // namespace
 
+template <typename T>
+int seed_density(ek_ctx* c, Sim<T>& s, uint64_t seed, double noise) {
+    SeedArgs a{};
+    a.seed = seed;
+    a.noise = noise;
+    a.fac = field_factor(c, EK_FIELD_DENSITY);
+    for (int k = 0; k < c->p.n_species; ++k) a.mean[k] = c->p.species[k].mean_density;
+    launch_seed_density(s, a, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return EK_OK;
+}
+
 extern "C" {
 
 const char* ek_strerror(int code) {
@@ -727,6 +740,12 @@ int ek_set_fields(ek_ctx* c, int field, const void* host, size_t bytes) {
     if (!c || !host) return EK_ERR_INVALID_ARG;
     if (c->err) return c->err;
     return c->fp32 ? set_field(c, c->sf, field, host, bytes) : set_field(c, c->sd, field, host, bytes);
+}
+
+int ek_seed_density(ek_ctx* c, uint64_t seed, double noise) {
+    if (!c || !std::isfinite(noise) || std::fabs(noise) > 1.0) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    return c->fp32 ? seed_density(c, c->sf, seed, noise) : seed_density(c, c->sd, seed, noise);
 }
 
 int ek_prepare(ek_ctx* c) {
@@ -1057,9 +1076,17 @@ int ek_batch_create(size_t arena_bytes, int n_species, void* stream, void* arena
     return EK_OK;
 }
 
-int ek_batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
-                   const double* initial_density, long long n_steps, int* slot) {
+namespace {
+struct SeedSpec {
+    bool on;
+    uint64_t seed;
+    double noise;
+};
+
+int batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
+                const double* initial_density, const SeedSpec& sd, long long n_steps, int* slot) {
     if (!b || !p || (n_spheres > 0 && !spheres) || n_spheres < 0 || n_steps < 0) return EK_ERR_INVALID_ARG;
+    if (sd.on && (!std::isfinite(sd.noise) || std::fabs(sd.noise) > 1.0)) return EK_ERR_INVALID_ARG;
     if (b->err) return b->err;
     if (p->precision != EK_FP32_DEV || p->n_species != b->ns) return EK_ERR_INVALID_ARG;
     int i = 0;
@@ -1088,6 +1115,8 @@ int ek_batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, in
                           spheres[k].mode, nullptr);
     if (!r && initial_density)
         r = ek_set_fields(c, EK_FIELD_DENSITY, initial_density, (size_t)q.n_species * c->N * sizeof(double));
+    else if (!r && sd.on)
+        r = ek_seed_density(c, sd.seed, sd.noise);
     if (!r) r = ek_prepare(c);
     if (r) {
         ek_destroy(c);
@@ -1109,6 +1138,17 @@ int ek_batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, in
     b->dirty = true;
     if (slot) *slot = i;
     return EK_OK;
+}
+}  // namespace
+
+int ek_batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
+                   const double* initial_density, long long n_steps, int* slot) {
+    return batch_admit(b, p, spheres, n_spheres, initial_density, SeedSpec{false, 0, 0.0}, n_steps, slot);
+}
+
+int ek_batch_admit_seeded(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
+                          uint64_t seed, double noise, long long n_steps, int* slot) {
+    return batch_admit(b, p, spheres, n_spheres, nullptr, SeedSpec{true, seed, noise}, n_steps, slot);
 }
 
 int ek_batch_step(ek_batch* b, int k) {

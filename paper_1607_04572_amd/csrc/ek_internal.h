@@ -332,6 +332,15 @@ template <typename T> void launch_move(const Sim<T>& s, hipStream_t st, int init
 template <typename T> void launch_geometry(const Sim<T>& s, hipStream_t st, int init);
 template <typename T> void launch_boundary(const Sim<T>& s, hipStream_t st);
 template <typename T> void launch_init_density(const Sim<T>& s, hipStream_t st);
+// Seeded initial concentration, simulation units mean[k] (1 + noise (2U - 1)),
+// stored as the host path stores the same values (value / fac, minus the
+// reference density on the FP32 path).
+struct SeedArgs {
+    uint64_t seed;
+    double noise, fac;
+    double mean[MAXS];
+};
+template <typename T> void launch_seed_density(const Sim<T>& s, const SeedArgs& a, hipStream_t st);
 template <typename T> void launch_charge_poisson(const Sim<T>& s, hipStream_t st);
 // EK + LB update; `mid` (optional) is recorded between the EK and LB kernels,
 // or after the fused kernel where they are one.

@@ -36,6 +36,39 @@ void fill_pops(T* f, long npad, bool dev, hipStream_t st) {
     long blocks = (19 * npad + UT - 1) / UT;
     hipLaunchKernelGGL(k_fill_pops<T>, dim3((unsigned)blocks), dim3(UT), 0, st, f, npad, dev);
 }
+// splitmix64 finaliser (Steele, Lea and Flood, "Fast splittable pseudorandom
+// number generators", OOPSLA 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Counter stream (seed, k, cell): U = (splitmix64(cell ^ seed ^ k << 40) >> 11)
+// 2^-53, exact in FP64; the density is formed with one rounding per operation
+// in the order written (no contraction), so the stored values are the ones
+// the host conversion gives for the same formula evaluated in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_seed_density(Sim<T> s, SeedArgs a) {
+#pragma clang fp contract(off)
+    const long c = (long)blockIdx.x * 256 + threadIdx.x;
+    if (c >= s.N) return;
+    for (int k = 0; k < s.ns; ++k) {
+        const uint64_t key = a.seed ^ ((uint64_t)k << 40);
+        const double u = (double)(splitmix64((uint64_t)c ^ key) >> 11) * 0x1p-53;
+        const double v = a.mean[k] * (1.0 + a.noise * (2.0 * u - 1.0));
+        s.rho[s.cur][(long)k * s.N + c] = (T)(v / a.fac - (sizeof(T) == 4 ? s.rho_ref[k] : 0.0));
+    }
+}
+
+template <typename T>
+void launch_seed_density(const Sim<T>& s, const SeedArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_seed_density<T>, dim3((unsigned)((s.N + 255) / 256)), dim3(256), 0, st, s, a);
+}
+template void launch_seed_density<float>(const Sim<float>&, const SeedArgs&, hipStream_t);
+template void launch_seed_density<double>(const Sim<double>&, const SeedArgs&, hipStream_t);
+
 template void fill_pops<float>(float*, long, bool, hipStream_t);
 template void fill_pops<double>(double*, long, bool, hipStream_t);
 

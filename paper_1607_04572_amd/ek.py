@@ -74,12 +74,12 @@ class ek_diag(C.Structure):
 
 # ABI symbols declared in include/ek.h
 SYMBOLS = ["ek_query_footprint", "ek_create", "ek_add_sphere", "ek_set_static_boundary", "ek_set_fields",
-           "ek_prepare", "ek_step", "ek_get_fields", "ek_get_particles", "ek_get_diagnostics",
+           "ek_seed_density", "ek_prepare", "ek_step", "ek_get_fields", "ek_get_particles", "ek_get_diagnostics",
            "ek_get_state", "ek_set_state", "ek_profile_stages", "ek_copy_probe", "ek_synchronize",
            "ek_destroy", "ek_strerror"]
 STAGES = ["move", "geometry", "boundary", "poisson", "forces", "ek", "lb", "finish"]
-BATCH_SYMBOLS = ["ek_batch_create", "ek_batch_admit", "ek_batch_step", "ek_batch_poll", "ek_batch_collect",
-                 "ek_batch_get_fields", "ek_batch_active", "ek_batch_destroy"]
+BATCH_SYMBOLS = ["ek_batch_create", "ek_batch_admit", "ek_batch_admit_seeded", "ek_batch_step", "ek_batch_poll",
+                 "ek_batch_collect", "ek_batch_get_fields", "ek_batch_active", "ek_batch_destroy"]
 
 _LIB = None
 
@@ -100,6 +100,7 @@ def lib():
                                     P(C.c_double), C.c_int, P(C.c_int)]
         L.ek_set_static_boundary.argtypes = [vp, P(C.c_uint8), P(C.c_double)]
         L.ek_set_fields.argtypes = [vp, C.c_int, vp, C.c_size_t]
+        L.ek_seed_density.argtypes = [vp, C.c_uint64, C.c_double]
         L.ek_prepare.argtypes = [vp]
         L.ek_step.argtypes = [vp, C.c_int]
         L.ek_get_fields.argtypes = [vp, C.c_int, vp, C.c_size_t]
@@ -114,6 +115,8 @@ def lib():
         L.ek_batch_create.argtypes = [C.c_size_t, C.c_int, vp, vp, P(vp)]
         L.ek_batch_admit.argtypes = [vp, P(ek_params), P(ek_sphere), C.c_int, P(C.c_double), C.c_longlong,
                                      P(C.c_int)]
+        L.ek_batch_admit_seeded.argtypes = [vp, P(ek_params), P(ek_sphere), C.c_int, C.c_uint64, C.c_double,
+                                            C.c_longlong, P(C.c_int)]
         L.ek_batch_step.argtypes = [vp, C.c_int]
         L.ek_batch_poll.argtypes = [vp, P(C.c_int), C.c_int, P(C.c_int)]
         L.ek_batch_collect.argtypes = [vp, C.c_int, P(ek_particle), C.c_int, P(ek_diag)]
@@ -172,6 +175,10 @@ def ek_set_static_boundary(ctx, mask: np.ndarray, charge: np.ndarray | None = No
 def ek_set_fields(ctx, field, values: np.ndarray):
     v = np.ascontiguousarray(values, dtype=np.float64).reshape(-1)
     _check(lib().ek_set_fields(ctx, FIELDS.get(field, field), v.ctypes.data, v.nbytes), "ek_set_fields")
+
+
+def ek_seed_density(ctx, seed: int, noise: float):
+    _check(lib().ek_seed_density(ctx, int(seed), float(noise)), "ek_seed_density")
 
 
 def ek_prepare(ctx):
@@ -258,19 +265,32 @@ def ek_batch_create(arena_bytes: int, n_species: int, stream: int = 0, arena: in
     return h
 
 
-def ek_batch_admit(b, p: ek_params, spheres: list, initial_density, n_steps: int) -> int:
+def _sphere_array(spheres: list):
     arr = (ek_sphere * max(1, len(spheres)))()
     for k, sp in enumerate(spheres):
         for d in range(3):
             arr[k].x[d] = sp.x[d]
             arr[k].v[d] = sp.v[d]
         arr[k].radius, arr[k].charge, arr[k].mass, arr[k].mode = sp.R, sp.Z, sp.M, sp.mode
+    return arr
+
+
+def ek_batch_admit(b, p: ek_params, spheres: list, initial_density, n_steps: int) -> int:
+    arr = _sphere_array(spheres)
     rho = None
     if initial_density is not None:
         rho = np.ascontiguousarray(initial_density, dtype=np.float64).reshape(-1)
     slot = C.c_int(-1)
     _check(lib().ek_batch_admit(b, C.byref(p), arr, len(spheres), None if rho is None else _dptr(rho),
                                 int(n_steps), C.byref(slot)), "ek_batch_admit")
+    return slot.value
+
+
+def ek_batch_admit_seeded(b, p: ek_params, spheres: list, seed: int, noise: float, n_steps: int) -> int:
+    arr = _sphere_array(spheres)
+    slot = C.c_int(-1)
+    _check(lib().ek_batch_admit_seeded(b, C.byref(p), arr, len(spheres), int(seed), float(noise), int(n_steps),
+                                       C.byref(slot)), "ek_batch_admit_seeded")
     return slot.value
 
 
@@ -337,9 +357,15 @@ class EkBatch:
         self.h = ek_batch_create(arena_bytes, n_species, stream, arena)
         self.meta = {}
 
-    def admit(self, w, initial_density=None, n_steps=None) -> int:
+    def admit(self, w, initial_density=None, n_steps=None, seeded: bool = False) -> int:
+        """seeded: the workload's seeded initial densities built on the device
+        (the values of workloads.initial_densities(w), no host array)."""
         p = params_from_workload(w, max_particles=max(1, len(w.spheres)))
-        slot = ek_batch_admit(self.h, p, w.spheres, initial_density, w.steps if n_steps is None else n_steps)
+        steps = w.steps if n_steps is None else n_steps
+        if seeded:
+            slot = ek_batch_admit_seeded(self.h, p, w.spheres, w.seed, w.noise, steps)
+        else:
+            slot = ek_batch_admit(self.h, p, w.spheres, initial_density, steps)
         self.meta[slot] = w
         return slot
 
@@ -404,7 +430,7 @@ class EkSim:
     library's kernels."""
 
     def __init__(self, w, initial_density: np.ndarray | None = None, use_torch: bool = True,
-                 static_mask=None, static_charge=None):
+                 static_mask=None, static_charge=None, seeded: bool = False):
         self.w = w
         self.N = w.cells
         self.ns = len(w.species)
@@ -429,6 +455,8 @@ class EkSim:
             ek_set_static_boundary(self.ctx, static_mask, static_charge)
         if initial_density is not None:
             ek_set_fields(self.ctx, "density", initial_density)
+        elif seeded:  # workloads.initial_densities(w), built on the device
+            ek_seed_density(self.ctx, w.seed, w.noise)
 
     def prepare(self):
         ek_prepare(self.ctx)

@@ -21,12 +21,10 @@ from .ek import EkBatch, EkError
 def run(requests: list, arena_bytes: int = 24 << 30, chunk: int = 20, clock=time.perf_counter) -> dict:
     """requests: [(arrival_seconds, Workload)], sorted by arrival.
 
-    The host prepares the initial state of arrived requests (seeded
-    densities, tens of ms for a 128^3 box) while the device runs the current
-    chunk of batched steps, so that the device does not wait for it."""
+    A request's initial state (its seeded densities) is built on the device
+    at admission, so the host does no per-cell work for it."""
     batch = EkBatch(arena_bytes, n_species=len(requests[0][1].species))
     pending = collections.deque((t, i, w) for i, (t, w) in enumerate(sorted(requests, key=lambda r: r[0])))
-    ready = {}  # request index -> initial densities, prepared after arrival
     arrival = {}
     latency = []
     lups = 0
@@ -34,32 +32,16 @@ def run(requests: list, arena_bytes: int = 24 << 30, chunk: int = 20, clock=time
     done = 0
     n_req = len(requests)
     max_active = 0
-
-    def prepare_arrived(head):
-        """Initial densities of the first `head` arrived requests in the queue."""
-        now = clock() - t0
-        for n, (t_arr, i, w) in enumerate(pending):
-            if t_arr > now or n == head:
-                break
-            if i not in ready:
-                ready[i] = W.initial_densities(w)
-
     try:
         while done < n_req:
             now = clock() - t0
-            # admit everything that has arrived, in order, while it fits; once
-            # the device has work, only requests whose state is prepared (the
-            # others are prepared while the next chunk runs)
+            # admit everything that has arrived, in order, while it fits
             while pending and pending[0][0] <= now:
                 t_arr, i, w = pending[0]
-                if i not in ready and batch.active()[0] > 0:
-                    break
-                rho = ready.pop(i) if i in ready else W.initial_densities(w)
                 try:
-                    slot = batch.admit(w, initial_density=rho)
+                    slot = batch.admit(w, seeded=True)
                 except EkError as e:
                     if e.code == -6:  # no slot or memory: wait for a completion
-                        ready[i] = rho
                         break
                     raise
                 arrival[slot] = (t_arr, w)
@@ -68,7 +50,6 @@ def run(requests: list, arena_bytes: int = 24 << 30, chunk: int = 20, clock=time
             max_active = max(max_active, n_act)
             if n_act:
                 batch.step(chunk)
-                prepare_arrived(4)  # host work while the chunk runs
             elif pending:
                 wait = pending[0][0] - (clock() - t0)
                 if wait > 0:

@@ -109,3 +109,38 @@ def test_serve_loop_small_stream():
     res = serve.run(reqs, arena_bytes=8 << 30, chunk=10)
     say(res)
     assert res["requests"] == 12 and res["p99_s"] >= res["p50_s"] > 0 and res["mlups"] > 0
+
+
+def test_seeded_density_equals_host_recipe():
+    """Seeded initial densities built on the device (ek_seed_density) are the
+    values of the host recipe workloads.initial_densities, stored bit for bit
+    as the host-array path stores them: FP32 deviations and FP64 plain, a cell
+    count that is not a multiple of the 256-cell launch blocks, two seeds;
+    and the two states stay equal through steps."""
+    import dataclasses
+    sph = [W.Sphere(x=(9.0, 6.0, 6.0), R=3.0, Z=10.0, M=2 * W.sphere_volume(3.0))]
+    for prec, seed, shape in (("fp32", 5, (24, 18, 12)), ("fp64", 2 ** 40 + 3, (18, 12, 24))):
+        w = dataclasses.replace(W.c0(), shape=shape, precision=prec, spheres=sph, seed=seed, charge="psi")
+        say(f"case seeded density {prec} seed={seed} shape={w.shape}")
+        a = EkSim(w, initial_density=W.initial_densities(w))
+        b = EkSim(w, seeded=True)
+        assert np.array_equal(a.field("density"), b.field("density"))
+        a.step(4)
+        b.step(4)
+        for f in ("density", "populations", "phi", "velocity"):
+            assert np.array_equal(a.field(f), b.field(f)), f
+        a.close()
+        b.close()
+
+
+def test_seeded_admission_equals_host_array():
+    say("case seeded admission")
+    out = []
+    for seeded in (False, True):
+        b = EkBatch(2 << 30)
+        s = b.admit(C, seeded=True) if seeded else b.admit(C, initial_density=W.initial_densities(C))
+        b.step(9)
+        out.append({f: b.field(s, f) for f in ("density", "populations", "phi", "velocity", "flag")})
+        b.close()
+    for f in out[0]:
+        assert np.array_equal(out[0][f], out[1][f]), f
