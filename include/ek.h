@@ -231,11 +231,12 @@ const char* ek_strerror(int code);
 /* ---------------------------------------------------------------------------
  * Serving form: many independent FP32 simulations of different box sizes and
  * particle counts resident in one device arena and advanced together.  Each
- * kernel of a step runs once for the whole batch (persistent workgroups walk
- * the concatenated work of all slots), and the step is a HIP graph captured
- * once, so requests can be admitted and retired between steps without
- * re-capturing.  Every simulation's arithmetic is independent of the others:
- * a request gives the same bits alone and in any mix.
+ * kernel of a step runs once for the whole batch (its workgroups cover the
+ * concatenated work of all slots), and the step is a HIP graph, captured again
+ * when an admission or retirement changes the amount of work, so requests can
+ * be admitted and retired between steps.  Every simulation's arithmetic is
+ * independent of the others: a request gives the same bits alone and in any
+ * mix.
  * ------------------------------------------------------------------------- */
 typedef struct ek_batch ek_batch;
 

@@ -211,9 +211,10 @@ inline Grids<T> grids_of(const S& s) {
 
 // ---------------------------------------------------------------------------
 // Batched (serving) form: a table of FP32 simulations in device memory.  Each
-// batched kernel runs a fixed grid that walks, for its kernel kind, the
-// concatenated workgroups of all slots (start = prefix sums), so one fixed
-// launch sequence serves any mix and is captured once in a HIP graph.
+// batched kernel covers, for its kernel kind, the concatenated workgroups of
+// all slots (start = prefix sums): one workgroup per item (flat, grid = the
+// total) or a resident grid that walks them.  The launch sequence is captured
+// in a HIP graph and captured again when a kind's total changes.
 // ---------------------------------------------------------------------------
 constexpr int MAX_SLOTS = 64;
 struct BatchTable {

@@ -1149,7 +1149,7 @@ void launch_finish(const Sim<T>& s, hipStream_t st, bool and_move) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched particle kernels (persistent grids over a BatchTable)
+// Batched particle kernels (one workgroup per (particle, chunk) over a BatchTable)
 // ---------------------------------------------------------------------------
 constexpr int BATCH_PART_BLOCKS = 1024;
 constexpr int BATCH_SMALL_BLOCKS = 256;
