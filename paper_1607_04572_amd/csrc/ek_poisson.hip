@@ -3,8 +3,8 @@
 //
 // The charge density q = sum_k z_k rho_k + rho_b is transformed with
 // hand-written Stockham FFTs held in LDS (radix 8 with compile-time plans for
-// the power-of-two lengths 32-512, a run-time mixed-radix (4, 2, 3) plan for
-// the others), multiplied by
+// the power-of-two lengths 32-512 and for 48 and 96, a run-time mixed-radix
+// (4, 2, 3) plan for the others), multiplied by
 // the Green's function of the 7-point Laplacian, 4 pi lambda_B / K^2 with
 // K^2 = sum_d (2 - 2 cos(2 pi k_d / n_d)) and the k = 0 mode set to zero
 // (neutralising background), and transformed back.  Five passes over HBM:
@@ -191,7 +191,7 @@ __device__ __forceinline__ void stage(cpx<T>* a, int n, int P, int ld, int Ns, c
 // when S is a multiple of 8, or S = 1 with base a multiple of R and R
 // dividing 8 (then the LDS addresses of a butterfly share one register).
 template <int S, int R>
-__device__ __forceinline__ constexpr bool pad_splits() { return S % 8 == 0 || (S == 1 && R <= 8); }
+__device__ __forceinline__ constexpr bool pad_splits() { return S % 8 == 0 || (S == 1 && 8 % R == 0); }
 template <int S, int R>
 __device__ __forceinline__ constexpr int pad_step() { return S % 8 == 0 ? S + S / 8 : 1; }
 
@@ -250,9 +250,11 @@ __device__ __forceinline__ void stage_c(cpx<T>* a, int P, int ld, const cpx<T>* 
     __syncthreads();
 }
 
-// Radix plan of a power-of-two length: 8 while at least 8 remains, then 4 or 2.
+// Radix plan of a length 2^a 3^b: 8 while a factor 8 remains, then 4 or 2,
+// then the 3s (a radix-3 stage then has a stride that is a multiple of 8 or
+// takes the general store path).
 template <int M>
-constexpr int radix_of() { return M % 8 == 0 ? 8 : (M % 4 == 0 ? 4 : 2); }
+constexpr int radix_of() { return M % 8 == 0 ? 8 : (M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 3)); }
 
 // PC > 0: the pencil count is the compile-time PC (P is then ignored).
 template <typename T, int N, bool INV, int PC = 0, int NS = 1>
@@ -298,13 +300,13 @@ __device__ __forceinline__ const cpx<T>* stage_twiddles(cpx<T>* a, int data_elem
     return t;
 }
 
-// Compile-time plans for the power-of-two lengths from 32 to 512, the
-// runtime plan otherwise.
+// Compile-time plans for the lengths of EK_FFT_LENGTHS, the runtime plan
+// otherwise.
 template <typename T, bool INV>
 __device__ __forceinline__ void fft_any(cpx<T>* a, int n, int P, int ld, const cpx<T>* __restrict__ tw);
 
-// Pass bodies are instantiated for a compile-time length NC (a power of two
-// from 32 to 512, or 0: any length, known at run time) and, in the y and z
+// Pass bodies are instantiated for a compile-time length NC (one of
+// EK_FFT_LENGTHS, or 0: any length, known at run time) and, in the y and z
 // passes, a compile-time group width TCC (0: the width is known at run time).
 // With both known every index of the loads, stages and stores is a shift, a
 // mask or a constant offset.
@@ -640,10 +642,10 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int T
 }
 
 // ---------------------------------------------------------------------------
-// Dispatch on the pencil length: compile-time bodies for the powers of two
+// Dispatch on the pencil length: compile-time bodies for the listed lengths
 // from 32 to 512 (full groups), the run-time body otherwise.
 // ---------------------------------------------------------------------------
-#define EK_FFT_LENGTHS(X) X(32) X(64) X(128) X(256) X(512)
+#define EK_FFT_LENGTHS(X) X(32) X(48) X(64) X(96) X(128) X(256) X(512)
 
 template <typename T>
 __device__ __forceinline__ void x_fwd_any(const Sim<T>& s, int b, int P) {
@@ -769,7 +771,7 @@ static size_t batch_lds_yz() {
 }
 
 // Flat launches with the same length dispatch as the single-simulation
-// passes (compile-time bodies for the powers of two).
+// passes (compile-time bodies for the listed lengths).
 __global__ __launch_bounds__(FT) void kb_fft_x_fwd(const BatchTable* __restrict__ tab) {
     batch_run<KK_FFTX, FLAT_FFT>(tab, [](const Sim<float>& s, int b) { x_fwd_any<float>(s, b, fft_pencils_x(s.nx)); });
 }

@@ -4,7 +4,8 @@
   (8) and a 3-factor edge (12) on the others: every FFT plan length at its
   extreme, the x pass with four pencil pairs per workgroup, y/z tiles of a
   single or few kx columns.
-- 3-factor edges 384 and 192 (runtime radix plans with radix-3 stages).
+- 3-factor edges 384 and 192 (runtime radix plans with radix-3 stages), 48
+  and 96 (compile-time plans ending in a radix-3 stage), FP64 and FP32.
 - No particles at all (pure electrokinetic flow in a field).
 - A neutral sphere at rest in no field: the equilibrium must stay put.
 Each case is compared against the oracle after a few steps; flags, owners and
@@ -73,9 +74,16 @@ def test_max_edge_fp32(shape):
     run_case(sphere_case("max_edge32", shape, "fp32"), 4, ok32_strong_field)
 
 
-@pytest.mark.parametrize("shape", [(384, 12, 8), (8, 192, 24)])
+@pytest.mark.parametrize("shape", [(384, 12, 8), (8, 192, 24), (96, 48, 24), (24, 96, 48)])
 def test_three_factor_edges(shape):
     run_case(sphere_case("three_factor", shape, "fp64"), 4, ok64)
+
+
+@pytest.mark.parametrize("shape", [(96, 48, 24), (24, 96, 48)])
+def test_three_factor_edges_fp32(shape):
+    """Edges 48 and 96 take compile-time FFT plans with a radix-3 stage (the
+    serving boxes); 24 the run-time plan."""
+    run_case(sphere_case("three_factor32", shape, "fp32"), 4, ok32)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
