@@ -178,7 +178,7 @@ __host__ __device__ inline int spec_stride(int nx, int elem_bytes) {
 }
 // EK tiles: TXW x TYW cells per z-plane, ZC planes per workgroup.
 template <typename T> struct EKTile {
-    static constexpr int TXW = sizeof(T) == 4 ? 64 : 32, TYW = 4, ZC = 16;
+    static constexpr int TXW = 32, TYW = sizeof(T) == 4 ? 8 : 4, ZC = 16;
 };
 
 // Workgroups of each kernel for one simulation.
