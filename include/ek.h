@@ -23,6 +23,15 @@
  *   - Every function returns EK_OK (0) or a negative EK_ERR_* code; no call
  *     throws.  ek_strerror() names a code.  A device error is latched in the
  *     context and returned by every later call on it.
+ *   - The volume-of-fluid advection (Sec. III.C) displaces a cell by u tau and
+ *     intersects it with its 26 neighbours only, so the method needs every
+ *     velocity component below one cell per step.  The kernels test each
+ *     fluid cell's velocity (stream/collide) and each free sphere's (after
+ *     each kick) and latch EK_ERR_UNSTABLE (|u_d| >= 1) or EK_ERR_NONFINITE
+ *     (NaN or infinity) in a device status word; a sphere that fails stops
+ *     where it is.  The synchronising calls (ek_get_*, ek_synchronize) report
+ *     it, and ek_step reports it once the stream has passed the step that
+ *     latched it; from then on the context returns that code.
  *   - The library owns contexts and all device memory it allocates; the caller
  *     owns every host buffer passed in or out (it is read or written during
  *     the call only).  Device memory may instead be provided by the caller as
@@ -53,11 +62,15 @@ extern "C" {
 #define EK_OK 0
 #define EK_ERR_INVALID_ARG (-1)      /* null pointer, bad enum, size mismatch, bad value */
 #define EK_ERR_UNSUPPORTED_SIZE (-2) /* a box edge is not 2^a 3^b with a >= 1, or outside [8, 512] */
-#define EK_ERR_UNSTABLE (-3)         /* D tau/a^2 above the explicit-diffusion bound, or viscosity <= 0 */
-#define EK_ERR_OVERLAP (-4)          /* a sphere too large for the box */
+#define EK_ERR_UNSTABLE (-3)         /* D tau/a^2 above the explicit-diffusion bound, viscosity <= 0,
+                                        a sphere's initial speed of a cell per step or more; or
+                                        (latched by the device) a fluid or sphere velocity
+                                        component reached one cell per step */
+#define EK_ERR_OVERLAP (-4)          /* a sphere too large for the box, or intersecting another */
 #define EK_ERR_OOM (-5)              /* device allocation failed or the arena is too small */
 #define EK_ERR_NO_SPACE (-6)         /* no free slot / memory for a batched simulation */
-#define EK_ERR_NONFINITE (-7)        /* a NaN or infinity in host input */
+#define EK_ERR_NONFINITE (-7)        /* a NaN or infinity in host input; or (latched by the
+                                        device) in a fluid or sphere velocity or a global sum */
 #define EK_ERR_DEVICE (-8)           /* a HIP call failed (latched) */
 #define EK_ERR_STATE (-9)            /* call not allowed in the current state */
 
@@ -155,7 +168,10 @@ int ek_create(const ek_params* p, ek_ctx** out);
  * (charge = Z in units of e), mass, initial velocity v0 (may be NULL), and mode
  * EK_FREE / EK_PRESCRIBED / EK_FIXED.  Allowed before the first step only.
  * Returns its id in *id (may be NULL).  Errors: INVALID_ARG, OVERLAP (2R + 2
- * cells exceed an edge), STATE (after the first step or beyond max_particles). */
+ * cells exceed an edge, or the sphere intersects one already added: centres
+ * closer than the sum of the radii, minimum image), UNSTABLE (a component of
+ * v0 of one cell per step or more), STATE (after the first step or beyond
+ * max_particles). */
 int ek_add_sphere(ek_ctx* c, const double pos[3], double radius, double charge, double mass,
                   const double v0[3], int mode, int* id);
 
@@ -271,12 +287,15 @@ int ek_batch_admit_seeded(ek_batch* b, const ek_params* p, const ek_sphere* sphe
 /* Enqueue k batched steps; slots that reach their requested steps stop. */
 int ek_batch_step(ek_batch* b, int k);
 
-/* Slots whose requested steps are all done and not yet collected (at most
- * cap of them written to done_slots).  Synchronises. */
+/* Slots whose requested steps are all done, or whose simulation latched an
+ * error (it then stops stepping), and not yet collected (at most cap of them
+ * written to done_slots).  Synchronises. */
 int ek_batch_poll(ek_batch* b, int* done_slots, int cap, int* n_done);
 
 /* Copy a slot's particles (first n) and diagnostics (either may be NULL) and
- * free the slot and its memory.  Synchronises. */
+ * free the slot and its memory.  A slot whose simulation latched an error is
+ * freed without copying, and its code (EK_ERR_UNSTABLE or EK_ERR_NONFINITE)
+ * is returned.  Synchronises. */
 int ek_batch_collect(ek_batch* b, int slot, ek_particle* out, int n, ek_diag* diag);
 
 /* A field of a live slot, as ek_get_fields (tests).  Synchronises. */

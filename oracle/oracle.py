@@ -250,11 +250,18 @@ class OracleSim:
                            d(self.static_charge), u8(flag), i32(owner), d(psi), d(rhob))
 
     def particles(self) -> list:
+        """Per particle: centre x, velocity v, angular velocity w, and the total
+        force F and torque T of the last step with their parts (momentum
+        exchange F_hyd/T_hyd, electrostatic F_el/T_el, fluid destroyed/created
+        F_cov/T_cov; zero before the first step)."""
         out = []
         for k in range(self.np):
             q = self.pt[k]
-            out.append({"x": np.array(q.x[:]), "v": np.array(q.v[:]), "w": np.array(q.w[:]),
-                        "F": np.array(q.F[:]), "T": np.array(q.T[:])})
+            d = {"x": np.array(q.x[:]), "v": np.array(q.v[:]), "w": np.array(q.w[:]),
+                 "F": np.array(q.F[:]), "T": np.array(q.T[:])}
+            for key in ("F_hyd", "T_hyd", "F_el", "T_el", "F_cov", "T_cov"):
+                d[key] = np.array(self.last[key][k]) if key in self.last else np.zeros(3)
+            out.append(d)
         return out
 
     def step(self):

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -37,7 +38,7 @@ double d_max() {
 
 struct Layout {
     size_t f, rho, u, fext, phi, rhob, psi, flag, owner, owner_prev, psi_owner, spec, tw, k2, parts, scratch,
-        partial, diag, state_end, total;
+        partial, diag, status, state_end, total;
 };
 
 Layout make_layout(const ek_params* p, size_t ts) {
@@ -69,6 +70,7 @@ Layout make_layout(const ek_params* p, size_t ts) {
     L.scratch = take((size_t)DIAG_BLOCKS * NDIAG * sizeof(double));
     L.partial = take((size_t)PART_KINDS * mp * MAX_CHUNKS * PSTRIDE * sizeof(double));
     L.diag = take(64 * sizeof(double));
+    L.status = take(sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -117,6 +119,9 @@ struct ek_ctx {
     int err = EK_OK;
     bool use_graphs = true;
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    // pinned copy of the device status word, refreshed after each ek_step's
+    // launches, so that a later ek_step reports a latched error without waiting
+    uint32_t* host_status = nullptr;
     // unit conversion (simulation units per lattice unit)
     double a = 1, tau = 1, rf = 1;
     long N = 0;
@@ -138,6 +143,21 @@ struct ek_ctx {
     } while (0)
 
 namespace {
+
+// EK error code of device status bits (0: none).
+int status_error(uint32_t st) {
+    if (st & ST_NONFINITE) return EK_ERR_NONFINITE;
+    if (st & ST_UNSTABLE) return EK_ERR_UNSTABLE;
+    return EK_OK;
+}
+
+// After the stream has been synchronised: latch what the kernels reported.
+int check_status(ek_ctx* c) {
+    uint32_t st = 0;
+    HIPCHK(c, hipMemcpy(&st, c->arena + c->L.status, sizeof(st), hipMemcpyDeviceToHost));
+    if (int e = status_error(st)) c->err = e;
+    return c->err;
+}
 
 template <typename T>
 void setup_sim(ek_ctx* c, Sim<T>& s) {
@@ -200,6 +220,7 @@ void setup_sim(ek_ctx* c, Sim<T>& s) {
     s.k2[1] = k2 + p->nx;
     s.k2[2] = k2 + p->nx + p->ny;
     s.parts = (PState*)(A + L.parts);
+    s.status = (uint32_t*)(A + L.status);
     s.scratch = (double*)(A + L.scratch);
     s.partial = (double*)(A + L.partial);
     s.box_max = 0;
@@ -228,6 +249,7 @@ int init_fields(ek_ctx* c, Sim<T>& s) {
     fill<uint16_t>(s.owner, N, NO_OWNER, st);
     fill<uint16_t>(s.owner_prev, N, NO_OWNER, st);
     fill<uint16_t>(s.psi_owner, N, NO_OWNER, st);
+    HIPCHK(c, hipMemsetAsync(s.status, 0, sizeof(uint32_t), st));
     // FFT tables in FP64 on the host, rounded once to T
     int n[3] = {p->nx, p->ny, p->nz};
     std::vector<T> tw, k2;
@@ -428,6 +450,7 @@ int get_field(ek_ctx* c, Sim<T>& s, int field, void* host, size_t bytes) {
     long N = c->N;
     hipStream_t st = c->stream;
     HIPCHK(c, hipStreamSynchronize(st));
+    if (int e = check_status(c)) return e;
     bool dev = sizeof(T) == 4;
     double fac = field_factor(c, field);
     if (field == EK_FIELD_FLAG) {
@@ -547,6 +570,9 @@ int diagnostics(ek_ctx* c, Sim<T>& s, ek_diag* out) {
     double h[NDIAG];
     HIPCHK(c, hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (int e = check_status(c)) return e;
+    for (int k = 0; k < NDIAG; ++k)
+        if (!std::isfinite(h[k])) return c->err = EK_ERR_NONFINITE;
     double a = c->a, tau = c->tau, rf = c->rf;
     std::memset(out, 0, sizeof(*out));
     out->step = c->step;
@@ -689,6 +715,20 @@ int ek_add_sphere(ek_ctx* c, const double pos[3], double radius, double charge, 
         x = x - n[d] * std::floor(x / n[d]);
         if (x >= n[d]) x -= n[d];
         q.x[d] = x;
+    }
+    // no two spheres may intersect (minimum-image distance of the centres
+    // below the sum of the radii)
+    for (const PState& o : c->parts) {
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double dx = q.x[d] - o.x[d];
+            if (dx > 0.5 * n[d]) dx -= n[d];
+            else if (dx < -0.5 * n[d]) dx += n[d];
+            d2 += dx * dx;
+        }
+        if (d2 < (R + o.R) * (R + o.R)) return EK_ERR_OVERLAP;
+    }
+    for (int d = 0; d < 3; ++d) {
         q.v[d] = (v0 && mode != EK_FIXED) ? v0[d] * tau / a : 0.0;
         if (std::fabs(q.v[d]) >= 1.0) return EK_ERR_UNSTABLE;
     }
@@ -762,7 +802,21 @@ int ek_step(ek_ctx* c, int n) {
         int r = ek_prepare(c);
         if (r) return r;
     }
-    return c->fp32 ? run_steps(c, c->sf, n) : run_steps(c, c->sd, n);
+    if (!c->host_status) {
+        if (hipHostMalloc((void**)&c->host_status, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->host_status = nullptr;
+            return EK_ERR_OOM;
+        }
+        *c->host_status = 0;
+    }
+    // what the device reported up to the last completed ek_step
+    if (int e = status_error(__atomic_load_n(c->host_status, __ATOMIC_RELAXED))) return c->err = e;
+    int r = c->fp32 ? run_steps(c, c->sf, n) : run_steps(c, c->sd, n);
+    if (r) return r;
+    HIPCHK(c, hipMemcpyAsync(c->host_status, c->arena + c->L.status, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                             c->stream));
+    return EK_OK;
 }
 
 int ek_profile_stages(ek_ctx* c, int n, double* ms_out, int n_out) {
@@ -790,7 +844,7 @@ int ek_synchronize(ek_ctx* c) {
     if (!c) return EK_ERR_INVALID_ARG;
     if (c->err) return c->err;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return EK_OK;
+    return check_status(c);
 }
 
 int ek_get_fields(ek_ctx* c, int field, void* host, size_t bytes) {
@@ -805,6 +859,7 @@ int ek_get_particles(ek_ctx* c, ek_particle* out, int n) {
     std::vector<PState> ps(c->parts.size());
     if (c->prepared && !ps.empty()) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (int e = check_status(c)) return e;
         PState* dp = c->fp32 ? c->sf.parts : c->sd.parts;
         HIPCHK(c, hipMemcpy(ps.data(), dp, ps.size() * sizeof(PState), hipMemcpyDeviceToHost));
     } else {
@@ -900,6 +955,7 @@ int ek_destroy(ek_ctx* c) {
             if (c->graph[i][j]) (void)hipGraphExecDestroy(c->graph[i][j]);
     if (c->own_arena && c->arena) (void)hipFree(c->arena);
     if (c->wall_charge) (void)hipFree(c->wall_charge);
+    if (c->host_status) (void)hipHostFree(c->host_status);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return EK_OK;
@@ -995,6 +1051,7 @@ int pull_state(ek_batch* b) {
         b->h.sims[i].cur = t->sims[i].cur;
         b->h.step[i] = t->step[i];
         b->h.active[i] = t->active[i];
+        b->h.status[i] = t->status[i];
         b->slot[i].ctx->set_cur(t->sims[i].cur);
         b->slot[i].ctx->step = t->step[i];
     }
@@ -1132,6 +1189,8 @@ int batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n
     s.size = need;
     s.cells = c->N;
     b->h.sims[i] = c->sf;
+    b->h.sims[i].status = (uint32_t*)((unsigned char*)b->dtab + offsetof(BatchTable, status)) + i;
+    b->h.status[i] = 0;
     b->h.step[i] = 0;
     b->h.target[i] = n_steps;
     b->h.active[i] = n_steps > 0 ? 1 : 0;
@@ -1194,7 +1253,7 @@ int ek_batch_poll(ek_batch* b, int* done_slots, int cap, int* n_done) {
     for (int i = 0; i < MAX_SLOTS; ++i) {
         ek_batch::Slot& s = b->slot[i];
         if (!s.used || s.reported || !s.on_device) continue;
-        if (b->h.step[i] >= b->h.target[i]) {
+        if (b->h.step[i] >= b->h.target[i] || b->h.status[i] != 0u) {
             if (n < cap) {
                 done_slots[n++] = i;
                 s.reported = true;
@@ -1219,15 +1278,20 @@ int ek_batch_collect(ek_batch* b, int slot, ek_particle* out, int n, ek_diag* di
     int r = pull_state(b);
     if (r) return r;
     ek_batch::Slot& s = b->slot[slot];
-    if (out && n > 0) r = ek_get_particles(s.ctx, out, n);
-    if (!r && diag) r = ek_get_diagnostics(s.ctx, diag);
-    if (r) return r;
+    // a simulation whose kernels latched an error is retired with that error
+    const int failed = s.on_device ? status_error(b->h.status[slot]) : EK_OK;
+    if (!failed) {
+        if (out && n > 0) r = ek_get_particles(s.ctx, out, n);
+        if (!r && diag) r = ek_get_diagnostics(s.ctx, diag);
+        if (r) return r;
+    }
     ek_destroy(s.ctx);
     range_free(b, s.off, s.size);
     s = ek_batch::Slot();
     b->h.active[slot] = 0;
+    b->h.status[slot] = 0;
     b->dirty = true;
-    return EK_OK;
+    return failed;
 }
 
 int ek_batch_active(ek_batch* b, int* n_active, long long* cells) {

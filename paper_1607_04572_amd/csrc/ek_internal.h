@@ -1,14 +1,20 @@
 // ek_internal.h -- device state layout and helpers of the gfx950 library.
 //
-// Layout in HBM (per simulation, N = nx*ny*nz cells, x fastest):
-//   f[2][19][N]   populations, ping-pong (T = double, or float deviations f - w_i)
-//   rho[2][ns][N] solute densities, ping-pong (float path: deviation from the mean)
-//   u[3][N], fext[3][N], phi[N], rhob[N]         (T)
-//   psi[N] float  (multiples of 1/4096: exact in float)
-//   flag[N] u8    bit0 boundary now, bit1 boundary before this step's move, bit2 wall
+// Layout in HBM (per simulation, N = nx*ny*nz cells, x fastest; T = double on
+// the FP64 path, float on the FP32 path; Np = N rounded up to a multiple of
+// FB = 64 cells):
+//   f[2][Np/64][19][64]  populations, ping-pong, in blocks of 64 cells that hold
+//                        their 19 values contiguously (FP32: f_i - w_i)
+//   rho[2][ns][N]        solute densities, ping-pong (FP32: rho_k - mean_k)
+//   u[2][Np/64][3][64]   fluid velocity, double-buffered (EK reads u[cur], LB
+//                        writes u[cur^1]); fext[Np/64][3][64] force density
+//   phi[N], rhob[N]      potential, particle charge density (T)
+//   psi[N] float         partial volume (multiples of 1/4096: exact in float)
+//   flag[N] u8           bit0 boundary now, bit1 boundary before this step's
+//                        move, bit2 wall
 //   owner[N], owner_prev[N], psi_owner[N] u16
-//   spec[(nx/2+1)*ny*nz] complex T  (half spectrum for the Poisson solve)
-//   FFT tables, particle records (FP64), reduction scratch.
+//   spec[ny*nz][nxs]     complex T, half spectrum, rows padded to 128-byte lines
+//   FFT tables, particle records (FP64), status word, reduction scratch.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -31,6 +37,16 @@ constexpr int MAX_CHUNKS = 32;        // workgroups per particle box
 constexpr int BOX_CELLS_PER_THREAD = 2;  // box cells per thread of a box kernel (target)
 constexpr int PSTRIDE = 16;           // doubles per partial-sum record
 enum { PART_BOUNDARY = 0, PART_HYDRO = 1, PART_EL = 2, PART_KINDS = 3 };
+
+// Global-memory access through a device pointer. A pointer read from memory
+// (the batched kernels take every field pointer from a table) is flat to the
+// compiler, and a flat access also counts against the LDS wait counter: each
+// wait for an LDS result then also waits for every global load and store in
+// flight. Kernel-argument pointers are global already; the cast costs nothing.
+template <typename T> using gmem = __attribute__((address_space(1))) T;
+template <typename T> __device__ __forceinline__ T gld(const T* p) { return *(const gmem<T>*)p; }
+template <typename T> __device__ __forceinline__ void gst(T* p, T v) { *(gmem<T>*)p = v; }
+template <typename T> __device__ __forceinline__ void gst_nt(T* p, T v) { __builtin_nontemporal_store(v, (gmem<T>*)p); }
 
 // ---------------------------------------------------------------------------
 // Compile-time loops and lattice tables
@@ -123,11 +139,35 @@ struct Sim {
     T* tw[3];                 // twiddles e^{-2 pi i m/n}, interleaved, per axis
     T* k2[3];                 // 2 - 2 cos(2 pi m / n) per axis
     PState* parts;
+    uint32_t* status;         // device status word (ST_* bits), zero while the state is sound
     double* scratch;          // reductions
     double* partial;          // per-(particle, chunk) partial sums of the particle kernels
     int box_max;              // bound on cells of one particle box
     int nchunk;               // workgroups per particle box in the particle kernels
 };
+
+// ---------------------------------------------------------------------------
+// Device status: bits latched by the kernels that see a velocity the method
+// cannot take.  The volume-of-fluid advection intersects a cell displaced by
+// u tau with its neighbours only, so every component of a fluid or particle
+// velocity must stay below one cell per step; a NaN or infinity means the
+// state is lost.
+// ---------------------------------------------------------------------------
+constexpr uint32_t ST_UNSTABLE = 1u, ST_NONFINITE = 2u;
+
+// Status bits of a velocity (lattice units): 0 if every component is finite
+// and below 1 in magnitude.
+template <typename V>
+__device__ __forceinline__ uint32_t velocity_status(V x, V y, V z) {
+    if (fabs(x) < (V)1 && fabs(y) < (V)1 && fabs(z) < (V)1) return 0u;
+    return (isfinite(x) && isfinite(y) && isfinite(z)) ? ST_UNSTABLE : ST_NONFINITE;
+}
+
+// Latch status bits (a vector-memory atomic on the simulation's status word;
+// taken only on the rare path where a velocity fails the test).
+__device__ __forceinline__ void latch_status(uint32_t* st, uint32_t bits) {
+    __hip_atomic_fetch_or((gmem<uint32_t>*)st, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------------------
 // Launch geometry shared by the single-simulation and batched launches
@@ -223,6 +263,7 @@ struct BatchTable {
     long long step[MAX_SLOTS];       // steps done
     long long target[MAX_SLOTS];     // steps requested
     int start[KK_N][MAX_SLOTS + 1];  // workgroup prefix sums per kernel kind
+    uint32_t status[MAX_SLOTS];      // each slot's device status word (its Sim's status points here)
     Sim<float> sims[MAX_SLOTS];
 };
 
@@ -292,16 +333,6 @@ __device__ __forceinline__ void batch_run(const BatchTable* tab, F&& f) {
     if constexpr (FLAT) batch_one<KK>(tab, f);
     else batch_loop<KK>(tab, f);
 }
-
-// Global-memory access through a device pointer. A pointer read from memory
-// (the batched kernels take every field pointer from a table) is flat to the
-// compiler, and a flat access also counts against the LDS wait counter: each
-// wait for an LDS result then also waits for every global load and store in
-// flight. Kernel-argument pointers are global already; the cast costs nothing.
-template <typename T> using gmem = __attribute__((address_space(1))) T;
-template <typename T> __device__ __forceinline__ T gld(const T* p) { return *(const gmem<T>*)p; }
-template <typename T> __device__ __forceinline__ void gst(T* p, T v) { *(gmem<T>*)p = v; }
-template <typename T> __device__ __forceinline__ void gst_nt(T* p, T v) { __builtin_nontemporal_store(v, (gmem<T>*)p); }
 
 // i mod n for -n <= i < 2n (one conditional correction, no division).
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }

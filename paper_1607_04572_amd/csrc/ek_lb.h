@@ -147,6 +147,7 @@ __device__ __forceinline__ void lb_collide(const Sim<T>& s, uint32_t c, const Nb
         if constexpr (q19z(i) != 0) jz += (T)q19z(i) * pd[i];
     });
     const T ux = jx + (T)0.5 * fx, uy = jy + (T)0.5 * fy, uz = jz + (T)0.5 * fz;
+    if (const uint32_t bad = velocity_status(ux, uy, uz)) latch_status(s.status, bad);
     const T usq = ux * ux + uy * uy + uz * uz;
     const T uf = ux * fx + uy * fy + uz * fz;
     const T le = s.lam_e, lo = s.lam_o;

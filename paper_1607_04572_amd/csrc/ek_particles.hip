@@ -388,6 +388,12 @@ __device__ __forceinline__ void move_particle(const Sim<T>& s, int p, int init) 
                     q.v[d] += a * q.F[d] / q.M;
                     q.w[d] += a * q.T[d] / I;
                 }
+                if (const uint32_t bad = velocity_status(q.v[0], q.v[1], q.v[2])) {
+                    // one cell per step or more, or not finite: the error is latched and
+                    // the sphere stays where it is, so that its box stays in the lattice
+                    latch_status(s.status, bad);
+                    for (int d = 0; d < 3; ++d) q.v[d] = q.w[d] = 0.0;
+                }
             }
             for (int d = 0; d < 3; ++d) {
                 disp[d] = q.v[d];
@@ -966,6 +972,7 @@ __device__ __forceinline__ void finish_body(const Sim<T>& s, int bx_, int by_, i
             q.v[d] += 0.5 * Fn[d] / q.M;
             q.w[d] += 0.5 * Tn[d] / I;
         }
+        if (const uint32_t bad = velocity_status(q.v[0], q.v[1], q.v[2])) latch_status(s.status, bad);
     }
     for (int d = 0; d < 3; ++d) {
         q.F[d] = Fn[d];

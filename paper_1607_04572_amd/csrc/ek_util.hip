@@ -166,14 +166,15 @@ void launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
 }
 
 // End of a batched step: every active slot toggles its ping-pong buffers and
-// counts the step; a slot that reached its requested steps stops.
+// counts the step; a slot that reached its requested steps, or whose kernels
+// latched an error status, stops.
 __global__ void k_batch_flip(BatchTable* tab) {
     int i = threadIdx.x;
     if (i >= tab->nsims || !tab->active[i]) return;
     tab->sims[i].cur ^= 1;
     long long st = tab->step[i] + 1;
     tab->step[i] = st;
-    if (st >= tab->target[i]) tab->active[i] = 0;
+    if (st >= tab->target[i] || tab->status[i] != 0u) tab->active[i] = 0;
 }
 
 void launch_batch_flip(BatchTable* tab, hipStream_t st) {

@@ -430,11 +430,11 @@ class EkSim:
     library's kernels."""
 
     def __init__(self, w, initial_density: np.ndarray | None = None, use_torch: bool = True,
-                 static_mask=None, static_charge=None, seeded: bool = False):
+                 static_mask=None, static_charge=None, seeded: bool = False, max_particles: int | None = None):
         self.w = w
         self.N = w.cells
         self.ns = len(w.species)
-        p = params_from_workload(w)
+        p = params_from_workload(w, max_particles=max_particles)
         self._arena = None
         self._stream = None
         if use_torch:

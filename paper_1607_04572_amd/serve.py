@@ -32,6 +32,7 @@ def run(requests: list, arena_bytes: int = 24 << 30, chunk: int = 20, clock=time
     done = 0
     n_req = len(requests)
     max_active = 0
+    failed = 0
     try:
         while done < n_req:
             now = clock() - t0
@@ -56,17 +57,23 @@ def run(requests: list, arena_bytes: int = 24 << 30, chunk: int = 20, clock=time
                     time.sleep(min(wait, 0.01))
             for slot in batch.poll():
                 t_arr, w = arrival.pop(slot)
-                batch.collect(slot)
+                done += 1
+                try:
+                    batch.collect(slot)
+                except EkError as e:
+                    if e.code not in (-3, -7):  # unstable / non-finite: the request failed alone
+                        raise
+                    failed += 1
+                    continue
                 latency.append(clock() - t0 - t_arr)
                 lups += w.cells * w.steps
-                done += 1
         wall = clock() - t0
     finally:
         batch.close()
     lat = np.array(latency)
     return {"requests": n_req, "wall_s": wall, "mlups": lups / wall / 1e6,
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "max_active": max_active}
+            "mean_s": float(lat.mean()), "max_active": max_active, "failed": failed}
 
 
 def saturated_capacity(requests: list, arena_bytes: int = 24 << 30, chunk: int = 20) -> dict:

@@ -1,0 +1,118 @@
+"""GPU parity on paths the standard workloads do not reach, through the C ABI.
+
+- Solute expel fallbacks (Sec. III.D.1, read as: equal shares to the covered
+  cell's stable-fluid D3Q19 neighbours; with none, to its stable-fluid D3Q27
+  neighbours; with none either, uniformly over all stable-fluid cells).  Wall
+  cells from the static-boundary hook cage two cells in front of a moving
+  sphere: one cage is closed on all 26 sides (its cell's solute goes to the
+  global pool), the other leaves one corner open (its cell's solute goes to
+  that corner through the D3Q27 rule).
+- Simulation units other than the lattice's (a, tau, kT and the fluid density
+  all different from 1): the library converts the parameters, fields and
+  particle state; the oracle is fed the lattice-unit values.
+Bars as in the other parity tests."""
+import numpy as np
+import pytest
+
+from paper_1607_04572_amd import workloads as W
+from parity_util import compare, make_gpu, make_oracle, ok_fp32, ok_fp64, say
+
+pytestmark = pytest.mark.gpu
+
+N_CAGE = 16
+
+
+def _idx(x, y, z, n=N_CAGE):
+    return x + n * (y + n * z)
+
+
+def cage_mask():
+    """Walls on the 26 neighbours of (9, 8, 9), and on those of (9, 8, 11)
+    except its corner (10, 9, 12)."""
+    n = N_CAGE
+    m = np.zeros((n, n, n), np.uint8)  # [z, y, x]
+    for (x, y, z), opening in (((9, 8, 9), None), ((9, 8, 11), (1, 1, 1))):
+        for a in (-1, 0, 1):
+            for b in (-1, 0, 1):
+                for e in (-1, 0, 1):
+                    if (a, b, e) != (0, 0, 0) and (a, b, e) != opening:
+                        m[z + e, y + b, x + a] = 1
+    return m.reshape(-1)
+
+
+def cage_workload(precision):
+    return W.Workload(name=f"cage_{precision}", shape=(N_CAGE,) * 3, precision=precision,
+                      species=W.salt(0.3, 0.01), lambda_B=0.7, E=(0.01, 0.0, 0.0), steps=14,
+                      spheres=[W.Sphere(x=(5.0, 8.0, 10.0), R=2.5, Z=10.0, M=100.0, v=(0.25, 0.0, 0.0), mode=1)])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_expel_fallbacks_d3q27_and_pool(precision):
+    w = cage_workload(precision)
+    mask = cage_mask()
+    say(f"case {w.name}: caged cells in front of a moving sphere")
+    o = make_oracle(w, static_mask=mask)
+    g = make_gpu(w, static_mask=mask)
+    g.prepare()
+    c1, c2 = _idx(9, 8, 9), _idx(9, 8, 11)
+    nbr27 = [(a, b, e) for a in (-1, 0, 1) for b in (-1, 0, 1) for e in (-1, 0, 1) if (a, b, e) != (0, 0, 0)]
+    pooled_g = pooled_o = 0
+    pool_step = d3q27_step = None
+    for step in range(1, w.steps + 1):
+        flag_before = o.flag.copy()
+        g.step(1)
+        o.step()
+        pooled_g += g.diagnostics()["pooled"]
+        pooled_o += o.last["pooled"]
+        check = False
+        if o.flag[c1] and pool_step is None:
+            pool_step, check = step, True
+            assert o.last["pooled"] == 1
+        if o.flag[c2] and d3q27_step is None:
+            d3q27_step, check = step, True
+            # covered with no stable-fluid D3Q19 neighbour and one stable D3Q27 one
+            stable = [d for d in nbr27 if flag_before[_idx(9 + d[0], 8 + d[1], 11 + d[2])] == 0
+                      and o.flag[_idx(9 + d[0], 8 + d[1], 11 + d[2])] == 0]
+            assert stable == [(1, 1, 1)], stable
+        if check or step == w.steps:
+            e = compare(w, g, o, f"{w.name} step {step}")
+            ok_fp64(e, exact_positions=True) if precision == "fp64" else ok_fp32(e)
+    say("pooled", pooled_g, pooled_o, "pool step", pool_step, "D3Q27 step", d3q27_step)
+    assert pool_step is not None and d3q27_step is not None
+    assert pooled_o >= 1 and pooled_g == pooled_o
+    g.close()
+
+
+def units_workload(precision):
+    """Lattice spacing 0.5, time step 0.2, kT 2.5, fluid density 1.3; the
+    lattice values are nu 1/6, D 0.3, lambda_B 0.7, E 0.01, mean density
+    0.01, kT tau^2 / (rho a^5) = 2.4615."""
+    a, tau, rf = 0.5, 0.2, 1.3
+    D = 0.3 * a * a / tau
+    vol = W.sphere_volume
+    return W.Workload(
+        name=f"units_{precision}", shape=(24, 16, 18), precision=precision,
+        species=[W.Species(D, +1, 0.01 / a ** 3), W.Species(D * 0.8, -1, 0.012 / a ** 3)],
+        lambda_B=0.7 * a, E=(0.01 / a, 0.004 / a, 0.0), steps=20, nu=(1 / 6) * a * a / tau, kT=2.5,
+        fluid_density=rf, agrid=a, tau=tau,
+        spheres=[W.Sphere(x=(6.2 * a, 8.1 * a, 8.7 * a), R=3.2 * a, Z=20.0, M=2 * vol(3.2) * rf * a ** 3,
+                          v=(0.0, 0.0, 0.0), mode=0),
+                 W.Sphere(x=(17.3 * a, 7.6 * a, 9.4 * a), R=2.8 * a, Z=-12.0, M=150 * rf * a ** 3,
+                          v=(-0.12 * a / tau, 0.05 * a / tau, 0.0), mode=1)])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_simulation_units(precision):
+    w = units_workload(precision)
+    say(f"case {w.name}: a={w.agrid} tau={w.tau} kT={w.kT} rho_f={w.fluid_density}")
+    o = make_oracle(w)
+    g = make_gpu(w)
+    g.prepare()
+    done = 0
+    for cp in (1, 5, 20):
+        g.step(cp - done)
+        o.run(cp - done)
+        done = cp
+        e = compare(w, g, o, f"{w.name} step {cp}")
+        ok_fp64(e) if precision == "fp64" else ok_fp32(e)
+    g.close()

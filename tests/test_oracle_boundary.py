@@ -291,3 +291,149 @@ def test_initial_state_rule(pv):
     assert np.all(r[:, fl] == 0.0)
     expect = r0[:, ~fl] * ((1.0 - s.psi[~fl]) if pv else 1.0)
     assert np.array_equal(r[:, ~fl], expect)
+
+
+# -- angular momentum ----------------------------------------------------------
+def _arms(s):
+    """Cell-centre arms about the box centre o = L/2 per axis, without wrapping
+    (cell centres sit at i + 1/2, so every arm lies in (-L/2, L/2))."""
+    zz, yy, xx = np.meshgrid(np.arange(s.nz), np.arange(s.ny), np.arange(s.nx), indexing="ij")
+    return np.stack([xx.reshape(-1) + 0.5 - s.nx / 2, yy.reshape(-1) + 0.5 - s.ny / 2,
+                     zz.reshape(-1) + 0.5 - s.nz / 2])
+
+
+def _fluid_angular_momentum(s, arms):
+    mom = C19.T.astype(np.float64) @ s.f.reshape(19, -1)
+    fl = s.flag == 0
+    return np.cross(arms[:, fl].T, mom[:, fl].T).sum(axis=0)
+
+
+def _seam_term(s, f_prev, flag_prev):
+    """Streaming carries a population from x to x + c_i, so its arm changes by
+    c_i, parallel to its momentum, and its angular momentum is unchanged --
+    except where x + c_i crosses the periodic seam: there the arm jumps by
+    -+L_d e_d as well.  Sum of those jumps x momentum over the populations that
+    cross (all of them land in fluid cells here: the spheres stay clear of the
+    seam)."""
+    dims = (s.nx, s.ny, s.nz)
+    N = s.N
+    idx3 = np.stack(np.unravel_index(np.arange(N), (s.nz, s.ny, s.nx))[::-1])  # x, y, z
+    f = f_prev.reshape(19, N)
+    W = np.zeros(3)
+    for i in range(1, 19):
+        c = C19[i]
+        shift = np.zeros((3, N))
+        for d in range(3):
+            t = idx3[d] + c[d]
+            shift[d] = np.where(t >= dims[d], -dims[d], np.where(t < 0, dims[d], 0))
+        cross = np.any(shift != 0, axis=0) & (flag_prev == 0)
+        if not cross.any():
+            continue
+        dest = [(idx3[d][cross] + c[d]) % dims[d] for d in range(3)]
+        assert np.all(s.flag[dest[0] + s.nx * (dest[1] + s.ny * dest[2])] == 0)
+        W += np.cross(shift[:, cross].T, c.astype(np.float64)).T @ f[i, cross]
+    return W
+
+
+def _angular_budget(s, steps):
+    """Check, step by step, that the fluid's angular momentum about the box
+    centre o changes by exactly what the coupling force density puts in, minus
+    what the particles receive through bounce-back (Eq. force) and the Aidun
+    destroy/create impulses, each about o:
+      L(n) - L(n-1) = sum_x (x - o) x f_ext(x)
+                      - sum_p [T_p + (x_p - o) x F_p]_(hyd + cov) + W_seam.
+    The momentum exchanged on a link from fluid cell x_f into boundary cell
+    r_b = x_f + c_i is parallel to c_i, so its arm may be taken at r_b (as the
+    particle's torque does) or at x_f (where the fluid loses it): the budget
+    closes exactly, and any error in the torque's arm, sign or cross product
+    opens it."""
+    arms = _arms(s)
+    o = np.array([s.nx / 2, s.ny / 2, s.nz / 2])
+    worst, scale = 0.0, 0.0
+    for _ in range(steps):
+        L0 = _fluid_angular_momentum(s, arms)
+        f_prev, flag_prev = s.f.copy(), s.flag.copy()
+        s.step()
+        L1 = _fluid_angular_momentum(s, arms)
+        fl = s.flag == 0
+        ext = np.cross(arms[:, fl].T, s.fext.reshape(3, -1)[:, fl].T).sum(axis=0)
+        Tp = np.zeros(3)
+        for k, q in enumerate(s.particles()):
+            F = s.last["F_hyd"][k] + s.last["F_cov"][k]
+            T = s.last["T_hyd"][k] + s.last["T_cov"][k]
+            Tp += T + np.cross(q["x"] - o, F)
+            scale = max(scale, np.abs(s.last["T_hyd"][k]).max(), np.abs(s.last["T_cov"][k]).max())
+        W = _seam_term(s, f_prev, flag_prev)
+        res = (L1 - L0) - (ext - Tp + W)
+        worst = max(worst, float(np.abs(res).max()))
+        scale = max(scale, float(np.abs(L1 - L0).max()), float(np.abs(ext).max()))
+    return worst, scale
+
+
+def test_angular_momentum_budget_spinning_translating_sphere():
+    """A prescribed sphere that spins and translates (cells covered and
+    vacated every few steps), charged, in salt with a field: the torque of
+    Eq. force and of the Aidun impulses against the fluid's angular momentum."""
+    s = sim(24, [dict(x=(12.3, 11.8, 12.1), R=3.6, Z=20, M=200, v=(0.11, 0.07, -0.05),
+                      w=(0.004, -0.003, 0.005), mode=1)], E=(0.01, 0.005, 0.0))
+    events = 0
+    worst, scale = 0.0, 0.0
+    for _ in range(4):
+        w_, sc = _angular_budget(s, 5)
+        events += s.last["covered"] + s.last["vacated"]
+        worst, scale = max(worst, w_), max(scale, sc)
+    assert scale > 1e-2 and events > 20
+    assert worst < 1e-12 * scale, (worst, scale)
+
+
+def test_angular_momentum_budget_free_spheres():
+    """Two free spheres (velocity Verlet) with forces on: charged, in salt and
+    a field, one of them given a spin; the torque they receive turns them."""
+    s = sim(24, [dict(x=(8.2, 12.3, 11.7), R=3.2, Z=25, M=150, v=(0.03, 0.0, 0.01), w=(0.0, 0.0, 0.01)),
+                 dict(x=(16.4, 11.6, 12.4), R=3.0, Z=-15, M=120, v=(-0.02, 0.01, 0.0))],
+            E=(0.02, 0.0, 0.01))
+    worst, scale = _angular_budget(s, 20)
+    assert scale > 1e-3
+    assert worst < 1e-12 * scale, (worst, scale)
+    assert all(np.abs(q["w"]).max() > 0 for q in s.particles())
+
+
+def test_angular_momentum_budget_fails_for_a_planted_arm_error():
+    """The budget is sensitive to the torque: adding a tenth of (x_p - o) x F
+    to the reported torque (an arm about the wrong point) opens it by far more
+    than the bar."""
+    s = sim(24, [dict(x=(13.3, 11.8, 12.1), R=3.6, Z=20, M=200, v=(0.11, 0.07, -0.05),
+                      w=(0.004, -0.003, 0.005), mode=1)], E=(0.01, 0.005, 0.0))
+    arms = _arms(s)
+    o = np.array([12.0, 12.0, 12.0])
+    s.run(3)
+    L0 = _fluid_angular_momentum(s, arms)
+    f_prev, flag_prev = s.f.copy(), s.flag.copy()
+    s.step()
+    L1 = _fluid_angular_momentum(s, arms)
+    fl = s.flag == 0
+    ext = np.cross(arms[:, fl].T, s.fext.reshape(3, -1)[:, fl].T).sum(axis=0)
+    q = s.particles()[0]
+    F = s.last["F_hyd"][0] + s.last["F_cov"][0]
+    T = s.last["T_hyd"][0] + s.last["T_cov"][0]
+    W = _seam_term(s, f_prev, flag_prev)
+    good = (L1 - L0) - (ext - (T + np.cross(q["x"] - o, F)) + W)
+    bad = (L1 - L0) - (ext - (T + 1.1 * np.cross(q["x"] - o, F)) + W)
+    assert np.abs(good).max() < 1e-12 * np.abs(T).max()
+    assert np.abs(bad).max() > 1e-6 * np.abs(T).max()
+
+
+def test_integrators_constant_torque():
+    """The angular velocity under a constant torque grows by T/I per step with
+    I = 2/5 M R^2 (both integrators), and the stored torque is the one given."""
+    for integ in (0, 1):
+        p = O.make_params(1000, 1000, 1000, 1 / 6, 1.0, 0.7, (0, 0, 0), [(0.1, 0)], integrator=integ)
+        pt = O.make_particles([dict(x=(100.0, 200.0, 300.0), w=(0.001, 0.0, -0.002), R=2.0, Z=0, M=4.0)])
+        T = np.array([0.003, -0.001, 0.002])
+        pt[0].T[:] = T
+        for _ in range(40):
+            O.move(p, pt)
+            O.finish(p, pt, np.zeros(3), T)
+        I = 0.4 * 4.0 * 2.0 ** 2
+        assert np.allclose(np.array(pt[0].w[:]), np.array([0.001, 0.0, -0.002]) + 40 * T / I, rtol=0, atol=1e-14)
+        assert np.array_equal(np.array(pt[0].T[:]), T)
