@@ -203,6 +203,22 @@ int ek_prepare(ek_ctx* c);
  * HIP graph and replayed).  Returns without waiting. */
 int ek_step(ek_ctx* c, int n);
 
+/* ek_step for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Enqueues
+ * the same kernels as ek_step (same results, bit for bit) directly on the
+ * context's stream -- no graph is built, nothing is allocated -- with the
+ * per-(particle, chunk) partial sums of the particle kernels in a fixed device
+ * array of 512 KiB that the library holds on each GPU for the life of the
+ * process.  The context must be prepared (ek_prepare or an earlier ek_step;
+ * EK_ERR_STATE otherwise).  EK_ERR_NO_SPACE when those partial sums, 3 x
+ * particles x workgroups per particle box x 128 bytes, exceed 512 KiB (64
+ * spheres of radius 6 take 295 KiB).  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other host threads, other streams)
+ * race and must be ordered by the caller.  The first call on a GPU resolves
+ * the array's address (no allocation).  Errors otherwise as ek_step; a
+ * status latched by the kernels is reported by the synchronising calls. */
+int ek_step_noalloc(ek_ctx* c, int n);
+
 /* Copy a field to a host buffer of exactly the listed size (synchronises). */
 int ek_get_fields(ek_ctx* c, int field, void* host, size_t bytes);
 

@@ -613,6 +613,23 @@ int seed_density(ek_ctx* c, Sim<T>& s, uint64_t seed, double noise) {
     return EK_OK;
 }
 
+namespace {
+// Steps enqueued directly on the stream (no graph, no allocation), the
+// particle partial sums in the fixed scratch array at `scratch`.
+template <typename T>
+void enqueue_steps_direct(ek_ctx* c, Sim<T>& s, int n, double* scratch) {
+    Sim<T> t = s;
+    t.partial = scratch;
+    const int par = s.cur;
+    for (int k = 0; k < n; ++k) {
+        t.cur = (par + k) & 1;
+        enqueue_step(c, t, k > 0, k < n - 1);
+    }
+    if (n & 1) c->set_cur(par ^ 1);
+    c->step += n;
+}
+}  // namespace
+
 extern "C" {
 
 const char* ek_strerror(int code) {
@@ -816,6 +833,22 @@ int ek_step(ek_ctx* c, int n) {
     if (r) return r;
     HIPCHK(c, hipMemcpyAsync(c->host_status, c->arena + c->L.status, sizeof(uint32_t), hipMemcpyDeviceToHost,
                              c->stream));
+    return EK_OK;
+}
+
+int ek_step_noalloc(ek_ctx* c, int n) {
+    if (!c || n < 0) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    if (!c->prepared) return EK_ERR_STATE;
+    const Sim<float>& sf = c->sf;
+    const size_t need = (size_t)PART_KINDS * (size_t)sf.np * (size_t)sf.nchunk * PSTRIDE * sizeof(double);
+    if (need > NOALLOC_SCRATCH_BYTES) return EK_ERR_NO_SPACE;
+    void* scratch = nullptr;
+    HIPCHK(c, noalloc_scratch(&scratch));
+    if (n == 0) return EK_OK;
+    if (c->fp32) enqueue_steps_direct(c, c->sf, n, (double*)scratch);
+    else enqueue_steps_direct(c, c->sd, n, (double*)scratch);
+    HIPCHK(c, hipGetLastError());
     return EK_OK;
 }
 

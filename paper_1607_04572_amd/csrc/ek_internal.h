@@ -396,4 +396,9 @@ void launch_batch_finish(const BatchTable* tab, hipStream_t st);
 void launch_batch_flip(BatchTable* tab, hipStream_t st);
 void launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
 
+// Allocation-free step: the particle kernels' partial sums in a fixed device
+// array of this many bytes per GPU (ek_noalloc.hip).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)512 << 10;
+hipError_t noalloc_scratch(void** out);
+
 }  // namespace ek

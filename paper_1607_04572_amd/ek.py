@@ -74,7 +74,7 @@ class ek_diag(C.Structure):
 
 # ABI symbols declared in include/ek.h
 SYMBOLS = ["ek_query_footprint", "ek_create", "ek_add_sphere", "ek_set_static_boundary", "ek_set_fields",
-           "ek_seed_density", "ek_prepare", "ek_step", "ek_get_fields", "ek_get_particles", "ek_get_diagnostics",
+           "ek_seed_density", "ek_prepare", "ek_step", "ek_step_noalloc", "ek_get_fields", "ek_get_particles", "ek_get_diagnostics",
            "ek_get_state", "ek_set_state", "ek_profile_stages", "ek_copy_probe", "ek_synchronize",
            "ek_destroy", "ek_strerror"]
 STAGES = ["move", "geometry", "boundary", "poisson", "forces", "ek", "lb", "finish"]
@@ -103,6 +103,7 @@ def lib():
         L.ek_seed_density.argtypes = [vp, C.c_uint64, C.c_double]
         L.ek_prepare.argtypes = [vp]
         L.ek_step.argtypes = [vp, C.c_int]
+        L.ek_step_noalloc.argtypes = [vp, C.c_int]
         L.ek_get_fields.argtypes = [vp, C.c_int, vp, C.c_size_t]
         L.ek_get_particles.argtypes = [vp, P(ek_particle), C.c_int]
         L.ek_get_diagnostics.argtypes = [vp, P(ek_diag)]
@@ -187,6 +188,10 @@ def ek_prepare(ctx):
 
 def ek_step(ctx, n: int):
     _check(lib().ek_step(ctx, int(n)), "ek_step")
+
+
+def ek_step_noalloc(ctx, n: int):
+    _check(lib().ek_step_noalloc(ctx, int(n)), "ek_step_noalloc")
 
 
 def ek_get_fields(ctx, field, n_cells: int, n_species: int = 1) -> np.ndarray:
