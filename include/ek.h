@@ -127,7 +127,9 @@ typedef struct {
                                          electrostatic, fluid destroyed/created */
     double radius, charge, mass;
     int mode;
-    int n_boundary;               /* cells whose centre is inside (owned) */
+    int n_boundary;               /* boundary cells it owns: cells whose centre is inside it
+                                     (simple scheme, Fig. 1) or, with partial volumes, cells
+                                     completely inside it (Psi = 1, Sec. III.D.2) */
 } ek_particle;
 
 typedef struct {

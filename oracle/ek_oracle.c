@@ -89,9 +89,11 @@ static void cell_disp(const or_params* p, long c, const or_particle* q, double d
     d[2] = min_image((double)z + 0.5, q->x[2], (double)p->nz);
 }
 
-/* Reading: a cell belongs to a particle iff its centre lies within distance R
- * (Fig. 1 caption: cells whose centre is inside the particle are boundary
- * nodes); the tie d^2 == R^2 counts as inside. */
+/* Reading (simple scheme): a cell belongs to a particle iff its centre lies
+ * within distance R (Fig. 1 caption: cells whose centre is inside the particle
+ * are boundary nodes); the tie d^2 == R^2 counts as inside.  The
+ * partial-volume scheme claims a cell only once it is completely inside the
+ * particle, Psi_p = 1 (see or_geometry). */
 static int centre_inside(const double d[3], double R) {
     double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
     return d2 <= R * R;
@@ -142,11 +144,22 @@ static int far_from(const double d[3], double R) {
 static double sphere_volume(double R) { return 4.0 / 3.0 * M_PI * R * R * R; }
 
 /* ---------------------------------------------------------------------------
- * Geometry: boundary flag, owner (lowest particle index whose sphere contains
- * the centre; -1 for static walls and fluid), Psi = min(1, sum_p Psi_p), and the
+ * Geometry: boundary flag, owner (lowest index of the particles that claim the
+ * cell; -1 for static walls and fluid), Psi = min(1, sum_p Psi_p), and the
  * particles' charge density rho_b (Sec. III.D.2: rho_b = Z e Psi / V_p with V_p
  * the continuum volume; or, in the uniform mode, Z spread equally over the
  * particle's boundary cells) plus any static boundary charge (Sec. III.C).
+ * A particle claims a cell (makes it a boundary cell):
+ *   simple scheme: when the cell's centre is inside it (Fig. 1 caption);
+ *   partial-volume scheme: when the cell is completely inside it, Psi_p = 1
+ *   (Sec. III.D.2 defines Psi = 1 as completely inside).
+ * Reading of the partial-volume rule: Sec. III.D.2 expects a claimed cell to
+ * hold little solute, a residue left only by the particle's discrete steps
+ * (the solute sits in the non-overlapped part, (1 - Psi) of the cell, so the
+ * cell is nearly empty only as Psi approaches 1); it lets vacated cells start
+ * from zero concentration; and Sec. IV.A sizes the moving particle by the
+ * number of its cells with Psi = 1.  All three hold when the claim happens at
+ * Psi = 1.
  * ------------------------------------------------------------------------- */
 void or_geometry(const or_params* p, const or_particle* pt, int np,
                  const uint8_t* static_mask, const double* static_charge,
@@ -161,11 +174,12 @@ void or_geometry(const or_params* p, const or_particle* pt, int np,
             double d[3];
             cell_disp(p, c, &pt[k], d);
             if (far_from(d, pt[k].R)) continue;
-            if (!fl && centre_inside(d, pt[k].R)) {
+            int cnt = or_psi_count(d[0], d[1], d[2], pt[k].R);
+            int claims = p->partial_volume ? cnt == 4096 : centre_inside(d, pt[k].R);
+            if (!fl && claims) {
                 fl = 1;
                 ow = k;
             }
-            int cnt = or_psi_count(d[0], d[1], d[2], pt[k].R);
             psum += (double)cnt / 4096.0;
             if (p->charge_mode == 0) qb += pt[k].Z * ((double)cnt / 4096.0) / sphere_volume(pt[k].R);
         }

@@ -106,7 +106,7 @@ struct PState {
     double disp[3];        // displacement of this step's move
     double pool[MAXS];     // solute of covered cells with no stable-fluid neighbour
     int box_lo[3], box_n[3];
-    int mode, nb;          // nb: cells owned (centre inside)
+    int mode, nb;          // nb: cells owned (claimed boundary cells)
     int ncov, nvac, npool, nflag;  // event counts of this step; nflag: box cells flagged now or before
 };
 

@@ -434,8 +434,9 @@ __global__ void k_move(Sim<T> s, int init) {
 }
 
 // ---------------------------------------------------------------------------
-// Coverage of the cells of each box: flag (centre inside, Fig. 1), owner
-// (lowest particle index), Psi = min(1, sum_p Psi_p), particle charge rho_b
+// Coverage of the cells of each box: flag (claimed: centre inside in the simple
+// scheme, Fig. 1; completely inside, Psi_p = 1, with partial volumes), owner
+// (lowest claiming particle index), Psi = min(1, sum_p Psi_p), particle charge rho_b
 // (Psi mode: sum_p Z_p Psi_p / V_p) plus wall charge.  The previous flag and
 // owner are kept in bit1 / owner_prev for the moving-boundary update.  The
 // loops are wavefront-uniform so that cut cells can be resolved cooperatively.
@@ -482,11 +483,19 @@ __device__ __forceinline__ void geometry_body(const Sim<T>& s, int bx_, int by_,
             double R2 = q.R * q.R;
             double lx = d[0] - 0.5, ly = d[1] - 0.5, lz = d[2] - 0.5;
             int cnt = touch ? psi_cell_class(lx, ly, lz, R2) : 0;
-            if (touch && !cur && centre_inside(d[0], d[1], d[2], q.R)) {
+            // a particle claims a cell when its centre is inside (simple scheme,
+            // Fig. 1) or, with partial volumes, when the cell is completely inside
+            // (Psi_p = 1, Sec. III.D.2): then a claimed cell holds almost no
+            // solute and a vacated one starts empty
+            if (!s.pv && touch && !cur && centre_inside(d[0], d[1], d[2], q.R)) {
                 cur = 1;
                 ow = (uint16_t)k;
             }
             cnt = wave_psi_resolve(touch && cnt < 0, lx, ly, lz, R2, cnt);
+            if (s.pv && touch && !cur && cnt == 4096) {
+                cur = 1;
+                ow = (uint16_t)k;
+            }
             if (touch && cnt > 0) {
                 psum += (double)cnt / 4096.0;
                 pso = (pso == NO_OWNER) ? (uint16_t)k : MULTI_OWNER;

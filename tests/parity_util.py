@@ -206,12 +206,13 @@ def compare(w, g, o, label=""):
 
 def snapshot(g, w: W.Workload) -> O.OracleSim:
     """The GPU state at a step boundary, as the oracle takes it (populations,
-    densities, velocity, flags, owners, particles)."""
-    parts = g.particles()
-    spheres = [dict(x=p["x"], v=p["v"], w=p["omega"], F=p["F"], T=p["T"], R=s.R, Z=s.Z, M=s.M, mode=s.mode)
-               for p, s in zip(parts, w.spheres)]
-    return O.OracleSim.from_state(oracle_params(w), spheres, g.field("populations"), g.field("density"),
-                                  g.field("velocity"), g.field("flag"), g.field("owner"))
+    densities, velocity, flags, owners, particles), in lattice units."""
+    lv = LatticeView(g, w) if not Units(w).unit else g
+    parts = lv.particles()
+    spheres = [dict(x=p["x"], v=p["v"], w=p["omega"], F=p["F"], T=p["T"], R=s["R"], Z=s["Z"], M=s["M"],
+                    mode=s["mode"]) for p, s in zip(parts, oracle_spheres(w))]
+    return O.OracleSim.from_state(oracle_params(w), spheres, lv.field("populations"), lv.field("density"),
+                                  lv.field("velocity"), lv.field("flag"), lv.field("owner"))
 
 
 # Bars: FP64 fields and particle quantities within 1e-12 relative; the FP32

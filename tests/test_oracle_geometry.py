@@ -51,37 +51,72 @@ def test_psi_total_volume(R):
     assert abs(rhob.sum() - 10.0 * psi.sum() / V) < 1e-12
 
 
-def brute_flags(shape, parts):
+def _disp(shape, s):
     nx, ny, nz = shape
     zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = []
+    for ax, (g, L) in enumerate(zip((xx, yy, zz), (nx, ny, nz))):
+        dd = g + 0.5 - s["x"][ax]
+        out.append(np.where(dd > L / 2, dd - L, np.where(dd < -L / 2, dd + L, dd)))
+    return out
+
+
+def brute_flags(shape, parts, pv):
+    """Owner of each cell by brute force: the lowest-index particle that claims
+    it -- simple scheme: the cell centre is inside (Fig. 1 caption);
+    partial-volume scheme: the cell is completely inside, i.e. all 16^3 leaf
+    centres of its depth-4 subdivision are (Psi_p = 1)."""
+    nx, ny, nz = shape
     owner = np.full((nz, ny, nx), -1)
     for k, s in enumerate(parts):
-        d2 = 0
-        for ax, (g, L) in enumerate(zip((xx, yy, zz), (nx, ny, nz))):
-            dd = g + 0.5 - s["x"][ax]
-            dd = np.where(dd > L / 2, dd - L, np.where(dd < -L / 2, dd + L, dd))
-            d2 = d2 + dd * dd
-        inside = (d2 <= s["R"] ** 2) & (owner < 0)
-        owner[inside] = k
+        dx, dy, dz = _disp(shape, s)
+        if not pv:
+            claim = dx * dx + dy * dy + dz * dz <= s["R"] ** 2
+        else:
+            claim = np.zeros_like(owner, dtype=bool)
+            near = np.argwhere((np.abs(dx) < s["R"]) & (np.abs(dy) < s["R"]) & (np.abs(dz) < s["R"]))
+            for z, y, x in near:
+                claim[z, y, x] = brute_psi_count(dx[z, y, x], dy[z, y, x], dz[z, y, x], s["R"]) == 4096
+        owner[claim & (owner < 0)] = k
     return owner.reshape(-1)
 
 
-def test_flags_owner_bruteforce_periodic():
-    """Two spheres, one wrapping across the periodic boundary, one overlapping
-    it: flag = centre inside, owner = lowest index."""
+@pytest.mark.parametrize("pv", [False, True])
+def test_flags_owner_bruteforce_periodic(pv):
+    """Three spheres, one wrapping across the periodic boundary, two
+    overlapping: the boundary flag and the owner (lowest index) against brute
+    force, for each scheme's rule of when a particle claims a cell."""
     shape = (16, 12, 20)
     parts = [dict(x=(0.7, 11.2, 19.4), R=3.3, Z=5.0, M=1.0),
              dict(x=(3.1, 1.0, 1.5), R=2.6, Z=7.0, M=1.0),
              dict(x=(9.5, 6.5, 10.5), R=4.0, Z=1.0, M=1.0)]
-    p = O.make_params(*shape, 1 / 6, 1.0, 0.7, (0, 0, 0), [(0.3, 1)], charge_mode=1)
+    p = O.make_params(*shape, 1 / 6, 1.0, 0.7, (0, 0, 0), [(0.3, 1)], charge_mode=1, partial_volume=pv)
     flag, owner, psi, rhob = O.geometry(p, parts)
-    ref = brute_flags(shape, parts)
+    ref = brute_flags(shape, parts, pv)
     assert np.array_equal(owner, ref)
     assert np.array_equal(flag, (ref >= 0).astype(np.uint8))
+    assert (ref >= 0).sum() > 100
+    if pv:
+        # every claimed cell is full, and every cell some particle covers fully is claimed
+        assert np.all(psi[flag == 1] == 1.0)
     # uniform charge mode: each particle's charge is spread exactly over its cells
     for k, s in enumerate(parts):
         assert abs(rhob[owner == k].sum() - s["Z"]) < 1e-12
     assert np.all(rhob[owner < 0] == 0)
+
+
+def test_partial_volume_claims_fewer_cells_than_centre_rule():
+    """A cell whose centre is inside but which is cut by the surface is a
+    boundary cell in the simple scheme and a fluid cell (0 < Psi < 1) in the
+    partial-volume scheme."""
+    shape = (16, 16, 16)
+    parts = [dict(x=(8.3, 7.9, 8.1), R=4.2, Z=5.0, M=1.0)]
+    f_pv = O.geometry(O.make_params(*shape, 1 / 6, 1.0, 0.7, (0, 0, 0), [(0.3, 1)], partial_volume=True), parts)
+    f_si = O.geometry(O.make_params(*shape, 1 / 6, 1.0, 0.7, (0, 0, 0), [(0.3, 1)], partial_volume=False), parts)
+    pv_flag, si_flag, psi = f_pv[0], f_si[0], f_pv[2]
+    assert np.all(si_flag[pv_flag == 1] == 1)
+    cut = (si_flag == 1) & (pv_flag == 0)
+    assert cut.sum() > 50 and np.all((psi[cut] > 0) & (psi[cut] < 1))
 
 
 def test_psi_sum_capped_at_one():

@@ -54,11 +54,13 @@ def _flagged_cells(L, centre, R):
     return int(np.sum((X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Zc - centre[2]) ** 2 <= R * R))
 
 
-def _frame_run(L, R, centre, mode, Z, E, steps, every):
-    """A charged sphere with its counterions (a neutral system, uniform charge on
-    the sphere's boundary cells) in a field E along x.  Returns per sample the
+def _frame_run(L, R, centre, mode, Z, E, steps, every, pv=True):
+    """A charged sphere with its counterions (a neutral system) in a field E
+    along x.  Returns per sample the
     sphere velocity, the mean fluid velocity along x and the flagged cell count."""
-    p = O.make_params(L, L, L, 1 / 6, 1.0, 0.7, (E, 0.0, 0.0), [(0.3, -1)], charge_mode=1, integrator=0)
+    # charge: Z Psi / V_p with partial volumes (Sec. III.D.2), else Z spread over the boundary cells
+    p = O.make_params(L, L, L, 1 / 6, 1.0, 0.7, (E, 0.0, 0.0), [(0.3, -1)], charge_mode=0 if pv else 1,
+                      integrator=0, partial_volume=pv)
     sph = [dict(x=centre, R=R, Z=Z, M=2 * (4 / 3) * np.pi * R ** 3, mode=mode)]
     N = L ** 3
     probe = O.OracleSim(p, sph, np.ones(N))
@@ -73,30 +75,40 @@ def _frame_run(L, R, centre, mode, Z, E, steps, every):
 
 
 @pytest.mark.slow
-def test_electrophoresis_matches_comoving_electroosmosis():
+@pytest.mark.parametrize("pv", [False])
+def test_electrophoresis_matches_comoving_electroosmosis(pv):
     """A freely moving charged sphere (electrophoresis) against the same sphere
     held fixed while its counterions drive the fluid past it (electro-osmosis,
     the co-moving frame): in the stationary state the sphere's speed relative to
     the bulk fluid is the same (Sec. IV, single-sphere comparison).  As in the
-    paper, the moving and the fixed particle are compared at the same effective
-    size: the fixed sphere's radius and lattice offset are chosen so that its
-    count of boundary cells matches the moving sphere's time average.  The paper
+    paper, the moving particle (partial-volume or simple scheme) and the fixed
+    one (the method with fixed boundaries: centre-inside cells) are compared at
+    the same effective size: the moving particle's boundary cells -- in the
+    partial-volume scheme the cells completely inside it -- are counted and
+    averaged over time, and the fixed sphere's radius and lattice offset are
+    chosen so that its count of boundary cells equals that average.  The paper
     reports agreement to 1.4 % (simple scheme) and 2.4 % (partial volumes); the
-    bar here is 3 % (observed 0.7 %)."""
+    bar here is 3 % (observed 1.4 %, simple scheme).  The partial-volume
+    comparison needs the paper's own system (Table I, 64^3, tens of thousands of
+    steps) and runs on the GPU: in boxes this small the cut shell, fluid to the
+    LB but partly closed to the solute, is a sizeable part of the particle, and
+    the two frames differ by 5-6 %."""
     L, Z, E = 16, 10.0, 0.01
     steps, every = 2400, 100
-    free = _frame_run(L, 3.0, (8.0, 8.0, 8.0), 0, Z, E, steps, every)
+    free = _frame_run(L, 3.0 if not pv else 3.6, (8.0, 8.0, 8.0), 0, Z, E, steps, every, pv=pv)
     half = len(free) // 2
     v_rel = np.mean(free[half:, 0] - free[half:, 1])   # sphere relative to the bulk fluid
     n_cells = np.mean(free[half:, 2])
     assert v_rel > 0.0                                   # a positive sphere moves along +E
     # fixed sphere of the same effective size
     cands = sorted((abs(_flagged_cells(L, c, R) - n_cells), round(R, 2), c)
-                   for R in np.arange(2.8, 3.3, 0.01)
+                   for R in np.arange(2.5, 3.6, 0.01)
                    for c in ((8.0, 8.0, 8.0), (8.5, 8.5, 8.5), (8.0, 8.5, 8.5), (8.0, 8.0, 8.5)))
     _, R_f, c_f = cands[0]
-    fixed = _frame_run(L, R_f, c_f, 2, Z, E, steps, every)
+    fixed = _frame_run(L, R_f, c_f, 2, Z, E, steps, every, pv=False)
     u_eo = fixed[:, 1]
+    print("pv", pv, "v_rel", v_rel, "boundary cells", n_cells, "fixed R", R_f, c_f, "EO", -u_eo[-1],
+          "ratio", v_rel / -u_eo[-1])
     assert abs(u_eo[-1] / u_eo[-5] - 1) < 1e-3         # the electro-osmotic flow is stationary
     assert np.all(fixed[:, 0] == 0.0)
     assert abs(v_rel / -u_eo[-1] - 1) < 0.03, (v_rel, -u_eo[-1], R_f, c_f, n_cells)
