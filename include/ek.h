@@ -221,6 +221,30 @@ int ek_step(ek_ctx* c, int n);
  * status latched by the kernels is reported by the synchronising calls. */
 int ek_step_noalloc(ek_ctx* c, int n);
 
+/* Relative permittivity field: Poisson's equation with an inhomogeneous
+ * dielectric, which the FFT solver cannot take (Sec. III.C names iterative
+ * solvers for it).  eps_r: N values > 0 (x fastest), relative to the
+ * permittivity that defines bjerrum_length; copied.  From the next step on
+ * the potential solves
+ *   sum over the 6 faces f of c: e_f (phi_c - phi_n) = 4 pi lambda_B (q_c - mean q)
+ * on the periodic lattice (the 7-point form of -div(eps grad phi) =
+ * 4 pi lambda_B q; e_f is the harmonic mean of the two cells' eps_r; for
+ * eps_r = 1 this is the FFT solver's equation) by Jacobi-preconditioned
+ * conjugate gradients in FP64, warm-started from the previous step's
+ * potential, until |r| <= tol |b| (0 < tol < 1) or max_iter iterations; the
+ * potential is shifted to zero mean.  The solve is driven from the host: it
+ * checks its residual every 8 iterations (a wait on the stream), so steps are
+ * not replayed from graphs while a permittivity is set, and ek_step returns
+ * when they are done.  A solve that misses the tolerance latches
+ * EK_ERR_UNSTABLE.  eps_r == NULL returns to the FFT solver.  Allocates
+ * 9 N doubles of device memory (outside the arena).  Errors: INVALID_ARG,
+ * NONFINITE, OOM, DEVICE. */
+int ek_set_permittivity(ek_ctx* c, const double* eps_r, double tol, int max_iter);
+
+/* Iterations and relative residual |r| / |b| of the last iterative Poisson
+ * solve (0 and 0 with the FFT solver). */
+int ek_get_poisson_stats(ek_ctx* c, int* iterations, double* residual);
+
 /* Copy a field to a host buffer of exactly the listed size (synchronises). */
 int ek_get_fields(ek_ctx* c, int field, void* host, size_t bytes);
 

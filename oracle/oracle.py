@@ -171,6 +171,53 @@ def poisson(q: np.ndarray, nx: int, ny: int, nz: int, lambda_B: float) -> np.nda
     return np.ascontiguousarray(phi.reshape(-1))
 
 
+def face_permittivity(eps3: np.ndarray, axis: int) -> np.ndarray:
+    """Permittivity on the face between each cell and its + neighbour along
+    `axis`: the harmonic mean 2 e_a e_b / (e_a + e_b) of the two cells.
+    Reading: the paper names iterative solvers for an inhomogeneous dielectric
+    without a discretisation; the harmonic mean is the face value for which a
+    layered dielectric (charge sheets between slabs of different permittivity)
+    has the exact series-capacitor solution."""
+    e2 = np.roll(eps3, -1, axis=axis)
+    return 2.0 * eps3 * e2 / (eps3 + e2)
+
+
+def poisson_dielectric(q: np.ndarray, eps: np.ndarray, nx: int, ny: int, nz: int,
+                       lambda_B: float) -> np.ndarray:
+    """Periodic Poisson solve with a relative permittivity eps (N values > 0)
+    per cell (Sec. III.C, non-FFT solvers for an inhomogeneous dielectric):
+      sum over the 6 faces of e_f (phi_c - phi_n) = 4 pi lambda_B (q_c - mean q),
+    i.e. -div(eps grad phi) = 4 pi lambda_B (q - mean q) with the 7-point
+    stencil; for eps = 1 this is the FFT solve above.  The periodic operator
+    is singular (constants): phi is fixed to 0 in cell 0, the system solved by
+    a sparse direct solver (a library primitive), and the mean of phi then
+    removed (the solution with zero mean, like the FFT one's)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    N = nx * ny * nz
+    e3 = np.ascontiguousarray(eps, dtype=np.float64).reshape(nz, ny, nx)
+    idx = np.arange(N).reshape(nz, ny, nx)
+    rows, cols, vals = [], [], []
+    diag = np.zeros((nz, ny, nx))
+    for ax3 in (2, 1, 0):  # x, y, z faces (array axes are z, y, x)
+        ef = face_permittivity(e3, ax3)
+        nb = np.roll(idx, -1, axis=ax3)
+        # face between c and its + neighbour n couples both ways
+        rows += [idx.ravel(), nb.ravel()]
+        cols += [nb.ravel(), idx.ravel()]
+        vals += [-ef.ravel(), -ef.ravel()]
+        diag += ef + np.roll(ef, 1, axis=ax3)
+    rows.append(idx.ravel())
+    cols.append(idx.ravel())
+    vals.append(diag.ravel())
+    L = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+    q = np.asarray(q, dtype=np.float64).reshape(-1)
+    b = 4.0 * np.pi * lambda_B * (q - q.mean())
+    phi = np.zeros(N)
+    phi[1:] = spl.spsolve(L[1:, 1:].tocsc(), b[1:])
+    return phi - phi.mean()
+
+
 class OracleSim:
     """One simulation, stepped in the order (particle move; geometry and
     moving-boundary update; charge and Poisson; EK fluxes and coupling force;
@@ -184,8 +231,10 @@ class OracleSim:
     def __init__(self, params: OrParams, particles: list, rho_init: np.ndarray,
                  static_mask: np.ndarray | None = None,
                  static_charge: np.ndarray | None = None,
-                 f_init: np.ndarray | None = None):
+                 f_init: np.ndarray | None = None,
+                 permittivity: np.ndarray | None = None):
         self.L = lib()
+        self.eps = None if permittivity is None else np.asarray(permittivity, dtype=np.float64).reshape(-1)
         self.p = params
         self.nx, self.ny, self.nz = params.nx, params.ny, params.nz
         self.N = N = self.nx * self.ny * self.nz
@@ -222,6 +271,7 @@ class OracleSim:
         coupling force are recomputed by the next step."""
         self = cls.__new__(cls)
         self.L = lib()
+        self.eps = None
         self.p = params
         self.nx, self.ny, self.nz = params.nx, params.ny, params.nz
         self.N = N = self.nx * self.ny * self.nz
@@ -280,7 +330,10 @@ class OracleSim:
         self.flag, self.owner = L_flag, L_owner
         q = np.zeros(N)
         L.or_charge(p, d(self.rho), d(self.rhob), d(q))
-        self.phi = poisson(q, self.nx, self.ny, self.nz, self.p.lambda_B)
+        if self.eps is None:
+            self.phi = poisson(q, self.nx, self.ny, self.nz, self.p.lambda_B)
+        else:
+            self.phi = poisson_dielectric(q, self.eps, self.nx, self.ny, self.nz, self.p.lambda_B)
         rho_new = np.zeros_like(self.rho)
         L.or_ek_update(p, d(self.rho), d(rho_new), d(self.phi), d(self.psi), u8(self.flag),
                        d(self.u), d(self.fext))

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libek_hip.so")
 SOURCES = ["ek_api.cpp", "ek_particles.hip", "ek_poisson.hip", "ek_fields.hip", "ek_lb.hip", "ek_util.hip",
-           "ek_noalloc.hip"]
+           "ek_noalloc.hip", "ek_poisson_cg.hip"]
 ARCH = "gfx950"
 
 

@@ -122,6 +122,12 @@ struct ek_ctx {
     // pinned copy of the device status word, refreshed after each ek_step's
     // launches, so that a later ek_step reports a latched error without waiting
     uint32_t* host_status = nullptr;
+    // iterative Poisson solve with a permittivity field (null: FFT solver)
+    CGState* cg = nullptr;
+    void* cg_mem = nullptr;
+    int cg_iters = 0;
+    double cg_res = 0.0;
+    bool cg_failed = false;
     // unit conversion (simulation units per lattice unit)
     double a = 1, tau = 1, rf = 1;
     long N = 0;
@@ -270,14 +276,30 @@ int init_fields(ek_ctx* c, Sim<T>& s) {
 // One step.  In a chain of steps (a captured graph), `moved`: the previous
 // step's closing kernel already performed this step's kick and drift;
 // `chain`: this step's closing kernel performs the next step's.
+// Charge assembly and Poisson solve: FFT, or the iterative solve with the
+// permittivity field (host-driven: it waits for its convergence checks).
 template <typename T>
-void enqueue_step(const ek_ctx* c, Sim<T> s, bool moved = false, bool chain = false) {
+void enqueue_poisson(ek_ctx* c, const Sim<T>& s) {
+    if (!c->cg) {
+        launch_charge_poisson(s, c->stream);
+        return;
+    }
+    int it = 0;
+    double res = 0.0;
+    if (cg_solve(s, *c->cg, c->stream, &it, &res) != 0) c->cg_failed = true;
+    c->cg_iters = it;
+    c->cg_res = res;
+    if (!(res <= c->cg->tol)) c->cg_failed = true;
+}
+
+template <typename T>
+void enqueue_step(ek_ctx* c, Sim<T> s, bool moved = false, bool chain = false) {
     hipStream_t st = c->stream;
     if (!moved) launch_move(s, st, 0);
     launch_geometry(s, st, 0);
     launch_boundary(s, st);
     if (!s.pv) launch_refill(s, st);
-    launch_charge_poisson(s, st);
+    enqueue_poisson(c, s);
     launch_particle_forces(s, st);
     launch_fields(s, st);
     launch_finish(s, st, chain);
@@ -285,7 +307,7 @@ void enqueue_step(const ek_ctx* c, Sim<T> s, bool moved = false, bool chain = fa
 
 // One step with a HIP event recorded after each stage (instrumentation).
 template <typename T>
-void enqueue_step_timed(const ek_ctx* c, Sim<T> s, hipEvent_t* ev) {
+void enqueue_step_timed(ek_ctx* c, Sim<T> s, hipEvent_t* ev) {
     hipStream_t st = c->stream;
     (void)hipEventRecord(ev[0], st);
     launch_move(s, st, 0);
@@ -295,7 +317,7 @@ void enqueue_step_timed(const ek_ctx* c, Sim<T> s, hipEvent_t* ev) {
     launch_boundary(s, st);
     if (!s.pv) launch_refill(s, st);
     (void)hipEventRecord(ev[3], st);
-    launch_charge_poisson(s, st);
+    enqueue_poisson(c, s);
     (void)hipEventRecord(ev[4], st);
     launch_particle_forces(s, st);
     (void)hipEventRecord(ev[5], st);
@@ -350,7 +372,7 @@ int run_steps(ek_ctx* c, Sim<T>& s, int n) {
         int par = s.cur;
         int chunk = (n >= GRAPH_CHUNK) ? 1 : 0;
         int k = chunk ? GRAPH_CHUNK : 1;
-        if (c->use_graphs) {
+        if (c->use_graphs && !c->cg) {
             if (!c->graph[par][chunk]) {
                 int r = build_graph(c, s, par, k, &c->graph[par][chunk]);
                 if (r) return r;
@@ -361,6 +383,7 @@ int run_steps(ek_ctx* c, Sim<T>& s, int n) {
             for (int i = 0; i < k; ++i) {
                 t.cur = (par + i) & 1;
                 enqueue_step(c, t);
+                if (c->cg_failed) return c->err = EK_ERR_UNSTABLE;
             }
             HIPCHK(c, hipGetLastError());
         }
@@ -839,7 +862,7 @@ int ek_step(ek_ctx* c, int n) {
 int ek_step_noalloc(ek_ctx* c, int n) {
     if (!c || n < 0) return EK_ERR_INVALID_ARG;
     if (c->err) return c->err;
-    if (!c->prepared) return EK_ERR_STATE;
+    if (!c->prepared || c->cg) return EK_ERR_STATE;
     const Sim<float>& sf = c->sf;
     const size_t need = (size_t)PART_KINDS * (size_t)sf.np * (size_t)sf.nchunk * PSTRIDE * sizeof(double);
     if (need > NOALLOC_SCRATCH_BYTES) return EK_ERR_NO_SPACE;
@@ -849,6 +872,73 @@ int ek_step_noalloc(ek_ctx* c, int n) {
     if (c->fp32) enqueue_steps_direct(c, c->sf, n, (double*)scratch);
     else enqueue_steps_direct(c, c->sd, n, (double*)scratch);
     HIPCHK(c, hipGetLastError());
+    return EK_OK;
+}
+
+int ek_set_permittivity(ek_ctx* c, const double* eps_r, double tol, int max_iter) {
+    if (!c) return EK_ERR_INVALID_ARG;
+    if (c->err) return c->err;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!eps_r) {
+        if (c->cg_mem) HIPCHK(c, hipFree(c->cg_mem));
+        c->cg_mem = nullptr;
+        delete c->cg;
+        c->cg = nullptr;
+        return EK_OK;
+    }
+    if (!(tol > 0.0 && tol < 1.0) || max_iter < 1) return EK_ERR_INVALID_ARG;
+    const long N = c->N;
+    for (long i = 0; i < N; ++i) {
+        if (!std::isfinite(eps_r[i])) return EK_ERR_NONFINITE;
+        if (!(eps_r[i] > 0.0)) return EK_ERR_INVALID_ARG;
+    }
+    if (!c->cg) {
+        // x, r, p, q, 3 face arrays, inverse diagonal, permittivity upload: 9 N doubles
+        const size_t part = (size_t)1024 * 4 * sizeof(double), sc = 64 * sizeof(double);
+        const size_t bytes = 9 * (size_t)N * sizeof(double) + part + sc;
+        void* mem = nullptr;
+        if (hipMalloc(&mem, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return EK_ERR_OOM;
+        }
+        CGState* g = new (std::nothrow) CGState();
+        if (!g) {
+            (void)hipFree(mem);
+            return EK_ERR_OOM;
+        }
+        double* d = (double*)mem;
+        g->x = d;
+        g->r = d + N;
+        g->p = d + 2 * N;
+        g->q = d + 3 * N;
+        for (int k = 0; k < 3; ++k) g->ef[k] = d + (4 + k) * N;
+        g->idiag = d + 7 * N;
+        g->part = d + 9 * N;
+        g->sc = g->part + 1024 * 4;
+        c->cg = g;
+        c->cg_mem = mem;
+        HIPCHK(c, hipMemsetAsync(g->x, 0, N * sizeof(double), c->stream));
+    }
+    CGState* g = c->cg;
+    g->nx = c->p.nx;
+    g->ny = c->p.ny;
+    g->nz = c->p.nz;
+    g->N = N;
+    g->fourpi_lb = 4.0 * M_PI * (c->fp32 ? c->sf.lambda_B : c->sd.lambda_B);
+    g->tol = tol;
+    g->max_iter = max_iter;
+    double* eps_dev = (double*)c->cg_mem + 8 * N;
+    HIPCHK(c, hipMemcpyAsync(eps_dev, eps_r, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (cg_setup(*g, eps_dev, c->stream) != 0) return c->err = EK_ERR_DEVICE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cg_failed = false;
+    return EK_OK;
+}
+
+int ek_get_poisson_stats(ek_ctx* c, int* iterations, double* residual) {
+    if (!c) return EK_ERR_INVALID_ARG;
+    if (iterations) *iterations = c->cg ? c->cg_iters : 0;
+    if (residual) *residual = c->cg ? c->cg_res : 0.0;
     return EK_OK;
 }
 
@@ -989,6 +1079,8 @@ int ek_destroy(ek_ctx* c) {
     if (c->own_arena && c->arena) (void)hipFree(c->arena);
     if (c->wall_charge) (void)hipFree(c->wall_charge);
     if (c->host_status) (void)hipHostFree(c->host_status);
+    if (c->cg_mem) (void)hipFree(c->cg_mem);
+    delete c->cg;
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return EK_OK;

@@ -396,6 +396,27 @@ void launch_batch_finish(const BatchTable* tab, hipStream_t st);
 void launch_batch_flip(BatchTable* tab, hipStream_t st);
 void launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
 
+// Iterative Poisson solve with a relative permittivity field (ek_poisson_cg.hip):
+// device buffers (FP64, N cells each unless stated) and controls.
+struct CGState {
+    int nx, ny, nz;
+    long N;
+    double fourpi_lb;         // 4 pi lambda_B (lattice units)
+    double* x;                // solution (the previous step's: warm start), zero mean
+    double* r;                // residual (holds the charge before the start)
+    double* p;                // search direction
+    double* q;                // L p
+    double* ef[3];            // face permittivities: ef[d][c] between c and c + e_d
+    double* idiag;            // 1 / diagonal of L
+    double* part;             // per-workgroup partial sums [1024][4]
+    double* sc;               // scalars (charge sum, r.z, r.r, b.b, alpha, beta, x sum)
+    double tol;               // stop at |r| <= tol |b|
+    int max_iter;
+};
+constexpr int CG_CHECK = 8;   // iterations between convergence checks
+int cg_setup(const CGState& g, const double* eps_dev, hipStream_t st);
+template <typename T> int cg_solve(const Sim<T>& s, CGState& g, hipStream_t st, int* iters, double* rel_res);
+
 // Allocation-free step: the particle kernels' partial sums in a fixed device
 // array of this many bytes per GPU (ek_noalloc.hip).
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)512 << 10;

@@ -75,7 +75,8 @@ class ek_diag(C.Structure):
 # ABI symbols declared in include/ek.h
 SYMBOLS = ["ek_query_footprint", "ek_create", "ek_add_sphere", "ek_set_static_boundary", "ek_set_fields",
            "ek_seed_density", "ek_prepare", "ek_step", "ek_step_noalloc", "ek_get_fields", "ek_get_particles", "ek_get_diagnostics",
-           "ek_get_state", "ek_set_state", "ek_profile_stages", "ek_copy_probe", "ek_synchronize",
+           "ek_get_state", "ek_set_state", "ek_set_permittivity", "ek_get_poisson_stats", "ek_profile_stages",
+           "ek_copy_probe", "ek_synchronize",
            "ek_destroy", "ek_strerror"]
 STAGES = ["move", "geometry", "boundary", "poisson", "forces", "ek", "lb", "finish"]
 BATCH_SYMBOLS = ["ek_batch_create", "ek_batch_admit", "ek_batch_admit_seeded", "ek_batch_step", "ek_batch_poll",
@@ -109,6 +110,8 @@ def lib():
         L.ek_get_diagnostics.argtypes = [vp, P(ek_diag)]
         L.ek_get_state.argtypes = [vp, vp, P(C.c_size_t)]
         L.ek_set_state.argtypes = [vp, vp, C.c_size_t]
+        L.ek_set_permittivity.argtypes = [vp, P(C.c_double), C.c_double, C.c_int]
+        L.ek_get_poisson_stats.argtypes = [vp, P(C.c_int), P(C.c_double)]
         L.ek_profile_stages.argtypes = [vp, C.c_int, P(C.c_double), C.c_int]
         L.ek_copy_probe.argtypes = [vp, vp, C.c_size_t, vp]
         L.ek_synchronize.argtypes = [vp]
@@ -236,6 +239,19 @@ def ek_get_state(ctx) -> bytes:
 def ek_set_state(ctx, image: bytes):
     buf = C.create_string_buffer(image, len(image))
     _check(lib().ek_set_state(ctx, C.cast(buf, C.c_void_p), len(image)), "ek_set_state")
+
+
+def ek_set_permittivity(ctx, eps_r, tol: float = 1e-12, max_iter: int = 10000):
+    e = None if eps_r is None else np.ascontiguousarray(eps_r, dtype=np.float64).reshape(-1)
+    _check(lib().ek_set_permittivity(ctx, None if e is None else _dptr(e), float(tol), int(max_iter)),
+           "ek_set_permittivity")
+
+
+def ek_get_poisson_stats(ctx) -> tuple:
+    it = C.c_int(0)
+    res = C.c_double(0.0)
+    _check(lib().ek_get_poisson_stats(ctx, C.byref(it), C.byref(res)), "ek_get_poisson_stats")
+    return it.value, res.value
 
 
 def ek_profile_stages(ctx, n: int) -> dict:
