@@ -5,9 +5,14 @@
 // k_ek: Nernst-Planck solute update (Sec. III.C, III.D.2).  For each cell, the
 //   flux on each of its 26 links is evaluated (13 directions, both ends), the
 //   density changes by the flux divergence, and the coupling force on the fluid
-//   is the friction of the diffusive/migrative part (Eq. fluidcoupling).  Both
-//   cells of a link evaluate it with identical operands and operation order, so
-//   the two evaluations are bitwise equal and solute is conserved link by link.
+//   is the friction of the diffusive/migrative part (Eq. fluidcoupling).  In
+//   the general form (ek_cell_update: FP64, and FP32 windows holding a
+//   boundary cell or a partial volume) both cells of a link evaluate it with
+//   identical operands and operation order, so the two evaluations are
+//   bitwise equal and solute is conserved link by link; FP32 windows free of
+//   both gather the same fluxes per neighbour in fewer operations
+//   (ek_cell_update_gather), conserving solute to the rounding of each cell's
+//   sums.
 //   Per link a -> b = a + s (s one of the 13 half-set directions):
 //     diffusive + migrative (the 9 D3Q19 links, Eq. flux-pv multiplied out):
 //       j = D/(A0|s|) [ rho_a(1-Psi_b) - rho_b(1-Psi_a)
@@ -17,6 +22,8 @@
 //     zero if either end is a boundary cell.
 //   The staged neighbourhood lives in LDS: a (TX+2) x (TY+2) x 3 window of every
 //   input field, marched along z.
+// k_ek32: the FP32 pass, with the loads of the window's next plane in flight
+//   while the current one is computed (ek_body_pipe).
 // k_ek<..., FUSE>: EK and LB in one pass: each thread finishes its cell's EK
 //   update and then streams/collides the same cell with the coupling force
 //   still in registers.  The velocity is double-buffered (EK reads u[cur], LB
@@ -58,6 +65,25 @@ struct EKConst {
 // 1 / (A0 |s|) of half-direction h (A0 = 1 + 2 sqrt 2).
 template <int H>
 constexpr double link_coef() { return 1.0 / ((1.0 + 2.0 * 1.4142135623730950488) * hlen(H)); }
+
+template <typename T, int NS>
+__device__ __forceinline__ EKConst<T, NS> ek_consts(const Sim<T>& s) {
+    EKConst<T, NS> K;
+    sfor<13>([&](auto HH) {
+        constexpr int h = HH;
+        K.Es[h] = (T)(s.E[0] * hx(h) + s.E[1] * hy(h) + s.E[2] * hz(h));
+    });
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        K.Dc[k][0] = (T)(s.D[k] * link_coef<0>());
+        K.Dc[k][1] = (T)(s.D[k] * link_coef<3>());
+        K.D[k] = (T)s.D[k];
+        K.hz[k] = (T)(0.5 * s.z[k]);
+        K.ref[k] = (T)s.rho_ref[k];
+        K.ref2hz[k] = (T)(0.5 * s.z[k]) * ((T)s.rho_ref[k] * (T)2);
+    }
+    return K;
+}
 
 // Fraction of a cell moving with velocity u that lands in the neighbour at
 // offset s along one axis: |u| if s has the sign of u, 1 - |u| if s = 0, else 0.
@@ -327,6 +353,85 @@ __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T
     });
 }
 
+// Clean-window update gathered per neighbour (FP32 path).  The same fluxes as
+// ek_cell_update, summed in another order: for the neighbours n = a + d of
+// cell a (26 of them), with R = r + mean the full density,
+//   advective: the outgoing part, sum_d R_a g(d; u_a), is R_a (1 - g(0; u_a))
+//     (a cell's fractions over its 27 destinations add up to one), so only
+//     the incoming parts R_n g(-d; u_n) are gathered;
+//   diffusive/migrative (D3Q19 d): g_k = (r_a - r_n) + z_k/2 (R_a + R_n)
+//     (phi_a - phi_n + E.d) is summed per link length, whose factor
+//     D_k/(A0|d|) is applied once;
+//   friction: sum_d d sum_k g_k, per link length.
+// Each link's flux is then not rounded on its own, so the two cells of a link
+// no longer hand over bitwise equal amounts: the species totals move by the
+// rounding of each cell's sums, ~1e-7 of that cell's fluxes.
+template <int NS, int TXW, int TYW>
+__device__ __forceinline__ void ek_cell_update_gather(const EKShared<float, NS, TXW, TYW>& sh, int s0, int sm,
+                                                      int sp, int ctr, const EKConst<float, NS>& K,
+                                                      float (&dr)[NS], float (&fe)[3]) {
+    using SH = EKShared<float, NS, TXW, TYW>;
+    const RecEK<float, NS> me = sh.get(s0, ctr);
+    float G[NS][2], adv[NS], hzC[NS], F[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}}, gin = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        G[k][0] = G[k][1] = adv[k] = 0.0f;
+        hzC[k] = K.hz[k] * (me.r(k) + K.ref[k] * 2.0f);  // z/2 (R_a + mean): the cell's share of z/2 (R_a + R_n)
+    }
+    sfor<13>([&](auto HH) {
+        constexpr int h = HH;
+        constexpr int c = hlen(h) > 1.0 ? 1 : 0;
+        auto one = [&](auto SG) {
+            constexpr int sg = SG;
+            constexpr int dx = sg * hx(h), dy = sg * hy(h), dz = sg * hz(h);
+            const int slot = dz == 0 ? s0 : (dz > 0 ? sp : sm);
+            const RecEK<float, NS> n = sh.get(slot, ctr + dy * SH::WX + dx);
+            const float gn = vof_frac<float, -dx, -dy, -dz>(n.ux(), n.uy(), n.uz());
+            gin += gn;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) adv[k] = __builtin_fmaf(n.r(k), gn, adv[k]);
+            if constexpr (h < 9) {
+                const float dphi = (me.phi() - n.phi()) + (sg > 0 ? K.Es[h] : -K.Es[h]);
+                float gs = 0.0f;
+#pragma unroll
+                for (int k = 0; k < NS; ++k) {
+                    const float m = __builtin_fmaf(K.hz[k], n.r(k), hzC[k]);
+                    const float g = __builtin_fmaf(m, dphi, me.r(k) - n.r(k));
+                    G[k][c] += g;
+                    gs = k == 0 ? g : gs + g;
+                }
+                if constexpr (dx > 0) F[c][0] += gs;
+                if constexpr (dx < 0) F[c][0] -= gs;
+                if constexpr (dy > 0) F[c][1] += gs;
+                if constexpr (dy < 0) F[c][1] -= gs;
+                if constexpr (dz > 0) F[c][2] += gs;
+                if constexpr (dz < 0) F[c][2] -= gs;
+            }
+        };
+        one(std::integral_constant<int, 1>{});
+        one(std::integral_constant<int, -1>{});
+    });
+    // Leaving fraction: the sum of the 26 fractions g(d; u_a) that the
+    // neighbours gather, with a_i = |u_i| and b_i = 1 - |u_i| rounded as
+    // there: a_x (a_y + b_y)(a_z + b_z) + b_x (a_y (a_z + b_z) + b_y a_z).
+    // (1 - b_x b_y b_z would carry the rounding of each b_i, ~1e-8 absolute,
+    // into every step's solute balance.)
+    const float ax = fabsf(me.ux()), ay = fabsf(me.uy()), az = fabsf(me.uz());
+    const float bx = vof_axis<float, 0>(me.ux()), by = vof_axis<float, 0>(me.uy()), bz = vof_axis<float, 0>(me.uz());
+    const float sz = az + bz;
+    const float out = __builtin_fmaf(ax, (ay + by) * sz, bx * __builtin_fmaf(ay, sz, by * az));
+    const float dg = gin - out;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        float d = __builtin_fmaf(-me.r(k), out, adv[k]);
+        d = __builtin_fmaf(K.ref[k], dg, d);
+        d = __builtin_fmaf(-K.Dc[k][1], G[k][1], d);
+        dr[k] = __builtin_fmaf(-K.Dc[k][0], G[k][0], d);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fe[d] = __builtin_fmaf((float)link_coef<3>(), F[1][d], (float)link_coef<0>() * F[0][d]);
+}
+
 // Boundary-cell sources of one cell's populations from the staged flags.
 template <typename T, int NS, int TXW, int TYW>
 __device__ __forceinline__ unsigned lb_bmask_lds(const EKShared<T, NS, TXW, TYW>& sh, int ctr, int s0, int sm,
@@ -363,20 +468,7 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
     const int x0 = bx * TXW, y0 = by * TYW, zbeg = bz * ZC;
     const T* __restrict__ rin = s.rho[s.cur];
     T* __restrict__ rout = s.rho[s.cur ^ 1];
-    EKConst<T, NS> K;
-    sfor<13>([&](auto HH) {
-        constexpr int h = HH;
-        K.Es[h] = (T)(s.E[0] * hx(h) + s.E[1] * hy(h) + s.E[2] * hz(h));
-    });
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        K.Dc[k][0] = (T)(s.D[k] * link_coef<0>());
-        K.Dc[k][1] = (T)(s.D[k] * link_coef<3>());
-        K.D[k] = (T)s.D[k];
-        K.hz[k] = (T)(0.5 * s.z[k]);
-        K.ref[k] = (T)s.rho_ref[k];
-        K.ref2hz[k] = (T)(0.5 * s.z[k]) * ((T)s.rho_ref[k] * (T)2);
-    }
+    const EKConst<T, NS> K = ek_consts<T, NS>(s);
     const T half_kT = (T)(0.5 * s.kT);
     const PlaneMap<T, NS, TXW, TYW> pm(s, x0, y0);
     {
@@ -412,8 +504,10 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
             T fe[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
             for (int k = 0; k < NS; ++k) dr[k] = (T)0;
-            if (clean)
-                ek_cell_update<T, DEV, NS, TXW, TYW, true>(s, sh, s0, sm, sp, ctr, K, dr, fe);
+            if (clean) {
+                if constexpr (sizeof(T) == 4 && DEV) ek_cell_update_gather<NS, TXW, TYW>(sh, s0, sm, sp, ctr, K, dr, fe);
+                else ek_cell_update<T, DEV, NS, TXW, TYW, true>(s, sh, s0, sm, sp, ctr, K, dr, fe);
+            }
             else if (!wall)
                 ek_cell_update<T, DEV, NS, TXW, TYW, false>(s, sh, s0, sm, sp, ctr, K, dr, fe);
             fe[0] *= half_kT;
@@ -445,12 +539,176 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 EK pass with the staging of the window pipelined: the loads of plane
+// z + 2 are issued into registers before plane z is computed and written to
+// LDS after it (into the slot of plane z - 1), so their latency hides behind
+// the flux work of the same workgroup.  Every thread holds the dirty mask of
+// the three staged planes (the result of the block-wide OR), so a plane costs
+// two barriers.
+// ---------------------------------------------------------------------------
+template <int NS, int TXW, int TYW>
+struct PlaneRegs {
+    static constexpr int NR = PlaneMap<float, NS, TXW, TYW>::NR;
+    float v[NR][NS + 5];  // densities, potential, Psi, velocity
+    uint8_t fl[NR];
+};
+
+template <int NS, int TXW, int TYW>
+__device__ __forceinline__ void plane_issue(const Sim<float>& s, const PlaneMap<float, NS, TXW, TYW>& pm, int z,
+                                            const float* __restrict__ rin, PlaneRegs<NS, TXW, TYW>& pr) {
+    using PM = PlaneMap<float, NS, TXW, TYW>;
+    using SH = EKShared<float, NS, TXW, TYW>;
+    const uint32_t zoff = (uint32_t)wrap1(z, s.nz) * ((uint32_t)s.nx * (uint32_t)s.ny);  // z in [-1, nz]
+    const float* __restrict__ ui = s.u[s.cur];
+#pragma unroll
+    for (int rr = 0; rr < PM::NR; ++rr) {
+        if ((rr + 1) * PM::NT > SH::WPL && threadIdx.x + rr * PM::NT >= SH::WPL) continue;
+        const uint32_t c = pm.at(s, rr) + zoff;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) pr.v[rr][k] = ld32(rin + (long)k * s.N, c);
+        pr.v[rr][NS] = ld32(s.phi, c);
+        pr.v[rr][NS + 1] = ld32(s.psi, c);
+        const float* uc = ui + vidx(0, c);
+        pr.v[rr][NS + 2] = gld(uc);
+        pr.v[rr][NS + 3] = gld(uc + FB);
+        pr.v[rr][NS + 4] = gld(uc + 2 * FB);
+        pr.fl[rr] = ld32(s.flag, c);
+    }
+}
+
+// Stage the loaded records; returns whether they hold a boundary cell or a
+// partial volume.
+template <int NS, int TXW, int TYW>
+__device__ __forceinline__ bool plane_commit(EKShared<float, NS, TXW, TYW>& sh, int slot,
+                                             const PlaneRegs<NS, TXW, TYW>& pr) {
+    using PM = PlaneMap<float, NS, TXW, TYW>;
+    using SH = EKShared<float, NS, TXW, TYW>;
+    // Every load of the plane has landed, on every path: without this wait
+    // (s_waitcnt vmcnt(0)) here, the compiler would see loads possibly in
+    // flight at the next plane's loads into the same registers and wait
+    // there, after this plane's stores.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    bool dirty = false;
+#pragma unroll
+    for (int rr = 0; rr < PM::NR; ++rr) {
+        const int t = threadIdx.x + rr * PM::NT;
+        if ((rr + 1) * PM::NT > SH::WPL && t >= SH::WPL) continue;
+        RecEK<float, NS> r;
+#pragma unroll
+        for (int k = 0; k < NS + 5; ++k) r.v[k] = pr.v[rr][k];
+        const bool wall = (pr.fl[rr] & F_CUR) != 0;
+        r.v[NS + 5] = wall ? 1.0f : 0.0f;
+#pragma unroll
+        for (int k = NS + 6; k < RecEK<float, NS>::NV; ++k) r.v[k] = 0.0f;
+        sh.put(slot, t, r);
+        dirty |= (pr.v[rr][NS + 1] != 0.0f) || wall;
+    }
+    return dirty;
+}
+
+// Block-wide OR of a predicate through one LDS word per wave.  (The runtime's
+// __syncthreads_or reads the block size from memory and so waits for every
+// outstanding vector memory operation, the stores of the plane just finished
+// and the loads of the plane being fetched among them.)  w must not be
+// written again before every wave has read it: callers alternate between
+// arrays separated by other barriers.
+template <int NW>
+__device__ __forceinline__ bool block_any(int (&w)[NW], bool p) {
+    const int wave_any = __any(p);
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = wave_any;
+    __syncthreads();
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r |= w[i];
+    return r != 0;
+}
+
+template <int NS, int TXW, int TYW>
+__device__ __forceinline__ void ek_body_pipe(const Sim<float>& s, int bx_, int ZC, int gx, int gy, int ntiles) {
+    using SH = EKShared<float, NS, TXW, TYW>;
+    constexpr int NW = TXW * TYW / 64;
+    __shared__ SH sh;
+    __shared__ int wany[3][NW];  // per slot, for block_any
+    const int tile = xcd_tile(bx_, ntiles);
+    const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+    const int x0 = bx * TXW, y0 = by * TYW, zbeg = bz * ZC;
+    const int zend = zbeg + ZC < s.nz ? zbeg + ZC : s.nz;
+    const float* __restrict__ rin = s.rho[s.cur];
+    float* __restrict__ rout = s.rho[s.cur ^ 1];
+    const EKConst<float, NS> K = ek_consts<float, NS>(s);
+    const float half_kT = (float)(0.5 * s.kT);
+    const PlaneMap<float, NS, TXW, TYW> pm(s, x0, y0);
+    PlaneRegs<NS, TXW, TYW> pr;
+    // planes zbeg - 1, zbeg, zbeg + 1 in slots (z + 3) mod 3
+    unsigned dm = 0;
+    for (int i = -1; i <= 1; ++i) {
+        plane_issue<NS, TXW, TYW>(s, pm, zbeg + i, rin, pr);
+        const int slot = (zbeg + i + 3) % 3;
+        dm |= (unsigned)block_any<NW>(wany[slot], plane_commit<NS, TXW, TYW>(sh, slot, pr)) << slot;
+    }
+    const int tx = threadIdx.x % TXW, ty = threadIdx.x / TXW;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool valid = x < s.nx && y < s.ny;
+    const int ctr = (ty + 1) * SH::WX + (tx + 1);
+    // One plane; MORE: a plane follows (stage plane z + 2).  The last plane is
+    // peeled off, so that on every path into the next plane's loads those of
+    // this plane have been waited for (else the wait before them would also
+    // cover this plane's stores).
+    auto plane = [&](int z, auto MORE) {
+        constexpr bool more = decltype(MORE)::value;
+        const int sm = (z + 2) % 3, s0 = z % 3, sp = (z + 1) % 3;
+        if constexpr (more) plane_issue<NS, TXW, TYW>(s, pm, z + 2, rin, pr);
+        float out[NS], fe[3] = {0.0f, 0.0f, 0.0f};
+        if (valid) {
+            const bool wall = sh.wall(s0, ctr);
+            float dr[NS];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) dr[k] = 0.0f;
+            if (dm == 0)
+                ek_cell_update_gather<NS, TXW, TYW>(sh, s0, sm, sp, ctr, K, dr, fe);
+            else if (!wall)
+                ek_cell_update<float, true, NS, TXW, TYW, false>(s, sh, s0, sm, sp, ctr, K, dr, fe);
+#pragma unroll
+            for (int k = 0; k < NS; ++k) out[k] = wall ? -K.ref[k] : sh.elem(s0, ctr, k) + dr[k];
+        }
+        // stage plane z + 2 over plane z - 1, then store this plane's results
+        // (issued after the wait for the staged loads, so that wait does not
+        // also cover these stores)
+        bool dnew = false;
+        if constexpr (more) {
+            __syncthreads();  // plane z - 1 (slot sm) is read no more
+            dnew = plane_commit<NS, TXW, TYW>(sh, sm, pr);
+        }
+        if (valid) {
+            const uint32_t c = cidx32(s, x, y, z);
+#pragma unroll
+            for (int k = 0; k < NS; ++k) st32_nt(rout + (long)k * s.N, c, out[k]);
+            float* fc = s.fext + vidx(0, c);
+            gst_nt(fc, fe[0] * half_kT);
+            gst_nt(fc + FB, fe[1] * half_kT);
+            gst_nt(fc + 2 * FB, fe[2] * half_kT);
+        }
+        if constexpr (more) dm = (dm & ~(1u << sm)) | ((unsigned)block_any<NW>(wany[sm], dnew) << sm);
+    };
+    for (int z = zbeg; z + 1 < zend; ++z) plane(z, std::true_type{});
+    plane(zend - 1, std::false_type{});
+}
+
 // At least two waves per SIMD: keeps the FP64 fused kernel from spilling into
 // accumulation registers past the 256-register budget of that occupancy.
 template <typename T, bool DEV, int NS, int TXW, int TYW, bool FUSE, bool PREFETCH>
 __global__ __launch_bounds__(TXW* TYW) __attribute__((amdgpu_waves_per_eu(2))) void k_ek(Sim<T> s, int ZC, int gx,
                                                                                           int gy, int ntiles) {
     ek_body<T, DEV, NS, TXW, TYW, FUSE, PREFETCH>(s, blockIdx.x, blockIdx.y, gridDim.x, ZC, gx, gy, ntiles);
+}
+
+// FP32.  (Capping it at 128 registers for a fourth wave per SIMD spills and
+// runs slower.)
+template <int NS, int TXW, int TYW>
+__global__ __launch_bounds__(TXW* TYW) void k_ek32(
+    Sim<float> s, int ZC, int gx, int gy, int ntiles) {
+    ek_body_pipe<NS, TXW, TYW>(s, blockIdx.x, ZC, gx, gy, ntiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -463,13 +721,43 @@ __global__ __launch_bounds__(TXW* TYW) __attribute__((amdgpu_waves_per_eu(2))) v
 template <typename T> constexpr bool kFuseFields = sizeof(T) == 8;
 template <typename T> constexpr bool kPrefetch = false;
 
+// Planes per workgroup of the FP32 EK pass: the tile columns are cut into as
+// many z-ranges as make the grid one full round of the workgroups the device
+// holds at once (a partial last round idles the rest of the chip, and each
+// range pays its three-plane prologue once), with at least MIN_ZC planes per
+// range.  Workgroups per CU and the CU count are queried once per process.
+template <int NS>
+static int ek32_planes(int columns, int nz) {
+    constexpr int TXW = EKTile<float>::TXW, TYW = EKTile<float>::TYW, MIN_ZC = 4;
+    static int slots = 0;
+    if (slots == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ek32<NS, TXW, TYW>, TXW * TYW, 0) != hipSuccess ||
+            cus <= 0 || per_cu <= 0)
+            return EKTile<float>::ZC;
+        slots = cus * per_cu;
+    }
+    int k = (slots + columns / 2) / columns;  // z-ranges per column
+    const int kmax = (nz + MIN_ZC - 1) / MIN_ZC;
+    k = k < 1 ? 1 : (k > kmax ? kmax : k);
+    return (nz + k - 1) / k;
+}
+
 template <typename T, bool DEV, int NS, bool FUSE>
 static void launch_ek_ns(const Sim<T>& s, hipStream_t st) {
     constexpr int TXW = EKTile<T>::TXW, TYW = EKTile<T>::TYW;
     Grids<T> g = grids_of<T>(s);
-    int nt = g.n[KK_EK];
-    hipLaunchKernelGGL((k_ek<T, DEV, NS, TXW, TYW, FUSE, kPrefetch<T>>), dim3(nt), dim3(TXW * TYW), 0, st, s,
-                       EKTile<T>::ZC, g.ek_gx, g.ek_gy, nt);
+    if constexpr (sizeof(T) == 4 && DEV && !FUSE) {
+        const int zc = ek32_planes<NS>(g.ek_gx * g.ek_gy, s.nz);
+        const int nt = g.ek_gx * g.ek_gy * ((s.nz + zc - 1) / zc);
+        hipLaunchKernelGGL((k_ek32<NS, TXW, TYW>), dim3(nt), dim3(TXW * TYW), 0, st, s, zc, g.ek_gx, g.ek_gy, nt);
+    } else {
+        const int nt = g.n[KK_EK];
+        hipLaunchKernelGGL((k_ek<T, DEV, NS, TXW, TYW, FUSE, kPrefetch<T>>), dim3(nt), dim3(TXW * TYW), 0, st, s,
+                           EKTile<T>::ZC, g.ek_gx, g.ek_gy, nt);
+    }
 }
 
 template <typename T, bool FUSE>
@@ -507,7 +795,7 @@ __attribute__((amdgpu_waves_per_eu(NS <= 2 ? 4 : 2))) void kb_ek(const BatchTabl
     batch_run<KK_EK, FLAT_EK>(tab, [](const Sim<float>& s, int b) {
         const int gx = (s.nx + TXW - 1) / TXW, gy = (s.ny + TYW - 1) / TYW;
         const int nt = gx * gy * ((s.nz + ZC - 1) / ZC);
-        ek_body<float, true, NS, TXW, TYW, kFuseFields<float>, kPrefetch<float>>(s, b, 0, 0, ZC, gx, gy, nt);
+        ek_body_pipe<NS, TXW, TYW>(s, b, ZC, gx, gy, nt);
     });
 }
 
