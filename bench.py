@@ -22,6 +22,10 @@ One JSON line is printed with the contract fields plus:
   effective     -- the state floor (populations and densities read and
                    written once, potential once each way) x MLUPS, vs 8 TB/s;
   kernels       -- per-stage mean times and algorithmic-byte bandwidths;
+                   particle_frac: the particle stages' share of the step;
+  boundary_cost -- step time with the spheres moving vs the same geometry
+                   fixed (static walls and charge), and partial-volume vs
+                   simple scheme, beside the paper's +2 % and < 10 %;
   fp64_plain    -- the same workload in FP64;
   serve         -- the serving loop: 200 seeded requests (box edge 32-128,
                    1-16 spheres, 1000 steps each) arriving as a Poisson stream
@@ -100,6 +104,46 @@ def run_gpu(w, steps: int, warmup: int, profile_steps: int):
     return dt, stages, diag
 
 
+PARTICLE_STAGES = ("move", "geometry", "boundary", "forces", "finish")
+
+
+def boundary_cost(w, steps: int, warmup: int) -> dict:
+    """Cost of the moving boundaries, beside the paper's figures (Sec. IV.A):
+    step time with the spheres moving vs the same geometry held fixed (the
+    boundary cells and particle charge of the first step as static walls and
+    static charge: no particle work), and with the partial-volume scheme vs
+    the simple one.  The three runs are timed alike, one after the other."""
+    import torch
+
+    from paper_1607_04572_amd.ek import EkSim
+
+    def timed(sim):
+        sim.prepare()
+        sim.step(warmup)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        sim.close()
+        torch.cuda.synchronize()
+        return ms
+
+    probe = EkSim(w, seeded=True)
+    probe.prepare()
+    mask, charge = probe.field("flag"), probe.field("particle_charge")
+    probe.close()
+    t_move = timed(EkSim(w, seeded=True))
+    t_fixed = timed(EkSim(w.replace(spheres=[]), seeded=True, static_mask=mask, static_charge=charge))
+    t_simple = timed(EkSim(w.replace(scheme="simple"), seeded=True))
+    torch.cuda.empty_cache()
+    return {"steps": steps, "moving_ms": t_move, "fixed_ms": t_fixed, "simple_ms": t_simple,
+            "moving_over_fixed": t_move / t_fixed, "pv_over_simple": t_move / t_simple,
+            "paper": {"moving_over_fixed": 1.02, "pv_over_simple_below": 1.10}}
+
+
 def copy_probe(mib: int, reps: int = 10) -> dict:
     """Plain device copy of `mib` MiB (the library's copy kernel), timed with
     HIP events: the achievable streaming bandwidth, and a kernel of known
@@ -160,6 +204,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-boundary-cost", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run the plain copy kernel on buffers of this size (counter calibration)")
@@ -200,10 +245,13 @@ def main():
         # the state floor: populations and densities read and written once, the potential once each way
         "effective": {"bytes_per_lup": state_bytes(w32, 4), "GBps": state_bytes(w32, 4) * mlups * 1e6 / 1e9,
                       "frac": state_bytes(w32, 4) * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
-        "kernels": {"stage_ms": stages, **{k: v for k, v in kern.items()}},
+        "kernels": {"stage_ms": stages, **{k: v for k, v in kern.items()},
+                    "particle_frac": sum(stages[k] for k in PARTICLE_STAGES) / sum(stages.values())},
         "diagnostics": {"species_total": [float(x) for x in diag["species_total"][:len(w32.species)]],
                         "max_velocity": diag["max_velocity"]},
     }
+    if not args.no_boundary_cost:
+        out["boundary_cost"] = boundary_cost(w32, min(args.steps, 100), args.warmup)
     if not args.no_fp64:
         w64 = w32.replace(precision="fp64", name=w32.name.replace("fp32", "fp64"))
         steps64 = max(10, args.steps // 2)

@@ -702,6 +702,34 @@ __device__ __forceinline__ void expel_cell(const Sim<T>& s, T* rho, int x, int y
     }
 }
 
+// Solute of covered cells with no stable-fluid neighbour in their whole
+// 26-neighbourhood is spread uniformly over all stable-fluid cells.  Exits at
+// once when there is none (the usual case).
+template <typename T>
+__device__ __forceinline__ void pool_body(const Sim<T>& s, int bx_, int by_, int gx_) {
+    // the usual case, nothing pooled, costs one flag per thread and one barrier
+    bool mine = false;
+    for (int q = threadIdx.x; q < s.np; q += PT) mine |= s.parts[q].npool != 0;
+    if (!__syncthreads_or(mine)) return;
+    double pool[MAXS] = {0.0, 0.0, 0.0, 0.0};
+    long nflag = 0;
+    for (int q = 0; q < s.np; ++q) {
+        const PState& pq = s.parts[q];
+        for (int k = 0; k < MAXS; ++k) pool[k] += pq.pool[k];
+        nflag += pq.nflag;
+    }
+    long nS = s.N - s.n_wall - nflag;
+    if (nS <= 0) return;
+    T* rho = s.rho[s.cur];
+    for (long c = (long)bx_ * PT + threadIdx.x; c < s.N; c += (long)gx_ * PT) {
+        if (!stable(s.flag[c])) continue;
+        for (int k = 0; k < s.ns; ++k) {
+            double v = rho_abs(s, rho, k, c) + pool[k] / (double)nS;
+            rho[(long)k * s.N + c] = (T)(sizeof(T) == 4 ? v - s.rho_ref[k] : v);
+        }
+    }
+}
+
 // Chunk partials of the boundary kernel -> particle record (by the first
 // workgroup of each particle), summed in chunk order.  Then covered cells lose
 // their solute and, in the uniform charge mode, each owned cell receives
@@ -750,6 +778,23 @@ __device__ __forceinline__ void boundary_post_body(const Sim<T>& s, int bx_, int
             s.rhob[c] = (T)qb;
         }
     }
+    if (!s.ticket) return;
+    // The last workgroup to finish runs the global pool (every particle
+    // record is final then; the pool writes only stable cells, which no
+    // workgroup here writes), which exits at once when nothing was pooled:
+    // no launch of its own in the usual case.  Release of this workgroup's
+    // writes, then its ticket (device-scope atomic).
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(s.ticket, 1u) == gridDim.x * gridDim.y - 1u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // acquire the other workgroups' records
+    if (threadIdx.x == 0) *s.ticket = 0u;  // every workgroup has taken its ticket
+    pool_body<T>(s, 0, 0, 1);
 }
 
 template <typename T>
@@ -757,38 +802,6 @@ __global__ __launch_bounds__(PT) void k_boundary_post(Sim<T> s) {
     boundary_post_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
-// Solute of covered cells with no stable-fluid neighbour in their whole
-// 26-neighbourhood is spread uniformly over all stable-fluid cells.  Exits at
-// once when there is none (the usual case).
-template <typename T>
-__device__ __forceinline__ void pool_body(const Sim<T>& s, int bx_, int by_, int gx_) {
-    // the usual case, nothing pooled, costs one flag per thread and one barrier
-    bool mine = false;
-    for (int q = threadIdx.x; q < s.np; q += PT) mine |= s.parts[q].npool != 0;
-    if (!__syncthreads_or(mine)) return;
-    double pool[MAXS] = {0.0, 0.0, 0.0, 0.0};
-    long nflag = 0;
-    for (int q = 0; q < s.np; ++q) {
-        const PState& pq = s.parts[q];
-        for (int k = 0; k < MAXS; ++k) pool[k] += pq.pool[k];
-        nflag += pq.nflag;
-    }
-    long nS = s.N - s.n_wall - nflag;
-    if (nS <= 0) return;
-    T* rho = s.rho[s.cur];
-    for (long c = (long)bx_ * PT + threadIdx.x; c < s.N; c += (long)gx_ * PT) {
-        if (!stable(s.flag[c])) continue;
-        for (int k = 0; k < s.ns; ++k) {
-            double v = rho_abs(s, rho, k, c) + pool[k] / (double)nS;
-            rho[(long)k * s.N + c] = (T)(sizeof(T) == 4 ? v - s.rho_ref[k] : v);
-        }
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(PT) void k_pool(Sim<T> s) {
-    pool_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
-}
 
 // Initial density rule: boundary cells empty; partial-volume fluid cells keep
 // (1 - Psi) of the given concentration.  Whole grid, once.
@@ -1124,8 +1137,7 @@ template <typename T>
 void launch_boundary(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
     hipLaunchKernelGGL(k_boundary<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
-    hipLaunchKernelGGL(k_boundary_post<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
-    hipLaunchKernelGGL(k_pool<T>, dim3(POOL_BLOCKS), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_boundary_post<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);  // and the pool
 }
 
 template <typename T>
