@@ -316,7 +316,8 @@ int ek_batch_create(size_t arena_bytes, int n_species, void* stream, void* arena
  * an optional initial density (n_species * N doubles, or NULL for the means)
  * and the number of steps to run.  Returns the slot.  EK_ERR_NO_SPACE when no
  * slot or no contiguous arena range of the request's footprint is free.
- * Synchronises the batch stream. */
+ * The request's state is built on a stream of the batch's own and waited
+ * for; the steps already queued keep running meanwhile. */
 int ek_batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
                    const double* initial_density, long long n_steps, int* slot);
 
@@ -326,18 +327,28 @@ int ek_batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, in
 int ek_batch_admit_seeded(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n_spheres,
                           uint64_t seed, double noise, long long n_steps, int* slot);
 
-/* Enqueue k batched steps; slots that reach their requested steps stop. */
+/* Enqueue a chunk of k batched steps; slots that reach their requested steps
+ * stop.  Slots admitted or collected since the last call join or leave the
+ * table in stream order, without waiting for the queued steps.  At most two
+ * chunks are queued ahead of the host: with two queued, the call first waits
+ * for the older one to finish. */
 int ek_batch_step(ek_batch* b, int k);
 
 /* Slots whose requested steps are all done, or whose simulation latched an
  * error (it then stops stepping), and not yet collected (at most cap of them
- * written to done_slots).  Synchronises. */
+ * written to done_slots), as of the chunks that have finished.  Does not
+ * wait: a slot finishing in a chunk still running is reported by a later
+ * call (or after ek_batch_wait). */
 int ek_batch_poll(ek_batch* b, int* done_slots, int cap, int* n_done);
+
+/* Wait for every queued chunk; ek_batch_poll then reports their outcome. */
+int ek_batch_wait(ek_batch* b);
 
 /* Copy a slot's particles (first n) and diagnostics (either may be NULL) and
  * free the slot and its memory.  A slot whose simulation latched an error is
  * freed without copying, and its code (EK_ERR_UNSTABLE or EK_ERR_NONFINITE)
- * is returned.  Synchronises. */
+ * is returned.  A slot reported by ek_batch_poll is read without waiting for
+ * the queued steps; any other slot first waits for them. */
 int ek_batch_collect(ek_batch* b, int slot, ek_particle* out, int n, ek_diag* diag);
 
 /* A field of a live slot, as ek_get_fields (tests).  Synchronises. */

@@ -1099,17 +1099,35 @@ int ek_destroy(ek_ctx* c) {
 struct ek_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t admit_stream = nullptr;  // admissions build their state here, beside the running batch
     unsigned char* arena = nullptr;
     size_t bytes = 0;
     bool own_arena = false;
-    BatchTable* dtab = nullptr;
+    BatchTable* dtab = nullptr;   // the live table
+    BatchTable* dup = nullptr;    // device staging of an upload (k_batch_merge's source)
+    BatchTable* hup = nullptr;    // pinned host staging of an upload
+    hipEvent_t up_ev = nullptr;   // the last upload's copy has been read
+    bool up_pending = false;
     std::map<size_t, size_t> free_ranges;  // offset -> size
     struct Slot {
         bool used = false, on_device = false, reported = false;
         ek_ctx* ctx = nullptr;
         size_t off = 0, size = 0;
         long long cells = 0;
+        unsigned epoch = 0;  // admissions into this slot index so far
     } slot[MAX_SLOTS];
+    // Host copies of the device-owned block taken after each chunk of steps
+    // (at most two chunks are queued ahead of the host).
+    struct Snap {
+        unsigned char* host = nullptr;  // pinned, BATCH_DEV_BYTES
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+        long long seq = 0;
+        bool on_dev[MAX_SLOTS];
+        unsigned epoch[MAX_SLOTS];
+    } snap[2];
+    long long seq = 0, applied = 0;  // chunks queued; newest chunk reflected in h
+    std::vector<std::pair<hipGraphExec_t, hipEvent_t>> retired;  // graphs possibly still queued
     BatchTable h{};
     int ns = 0;
     bool dirty = true;
@@ -1162,46 +1180,114 @@ void range_free(ek_batch* b, size_t off, size_t size) {
         }                             \
     } while (0)
 
-// Bring the device-owned parts (ping-pong index, steps, activity) of the
-// slots already on the device into the host mirror.
+// Device-owned entries (a copy of the block) into the host mirror and the
+// slots' contexts, for the slots that were on the device, with the same
+// occupant, when the copy was taken.
+void apply_dev(ek_batch* b, const unsigned char* blk, const bool* on_dev, const unsigned* epoch) {
+    int active[MAX_SLOTS], cur[MAX_SLOTS];
+    uint32_t status[MAX_SLOTS];
+    long long step[MAX_SLOTS];
+    std::memcpy(active, blk + offsetof(BatchTable, active), sizeof(active));
+    std::memcpy(cur, blk + offsetof(BatchTable, cur), sizeof(cur));
+    std::memcpy(status, blk + offsetof(BatchTable, status), sizeof(status));
+    std::memcpy(step, blk + offsetof(BatchTable, step), sizeof(step));
+    for (int i = 0; i < MAX_SLOTS; ++i) {
+        ek_batch::Slot& s = b->slot[i];
+        if (!s.used || !on_dev[i] || epoch[i] != s.epoch) continue;
+        b->h.active[i] = active[i];
+        b->h.cur[i] = cur[i];
+        b->h.sims[i].cur = cur[i];
+        b->h.status[i] = status[i];
+        b->h.step[i] = step[i];
+        s.ctx->set_cur(cur[i]);
+        s.ctx->step = step[i];
+    }
+}
+
+// Exact state: wait for everything queued, then read the block.
 int pull_state(ek_batch* b) {
     BCHK(b, hipStreamSynchronize(b->stream));
-    BatchTable* t = new (std::nothrow) BatchTable;
-    if (!t) return EK_ERR_OOM;
-    hipError_t e = hipMemcpy(t, b->dtab, sizeof(BatchTable), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) {
-        delete t;
-        b->err = EK_ERR_DEVICE;
-        return EK_ERR_DEVICE;
-    }
+    alignas(8) unsigned char blk[BATCH_DEV_BYTES];
+    BCHK(b, hipMemcpy(blk, b->dtab, BATCH_DEV_BYTES, hipMemcpyDeviceToHost));
+    bool on_dev[MAX_SLOTS];
+    unsigned epoch[MAX_SLOTS];
     for (int i = 0; i < MAX_SLOTS; ++i) {
-        if (!b->slot[i].used || !b->slot[i].on_device) continue;
-        b->h.sims[i].cur = t->sims[i].cur;
-        b->h.step[i] = t->step[i];
-        b->h.active[i] = t->active[i];
-        b->h.status[i] = t->status[i];
-        b->slot[i].ctx->set_cur(t->sims[i].cur);
-        b->slot[i].ctx->step = t->step[i];
+        on_dev[i] = b->slot[i].used && b->slot[i].on_device;
+        epoch[i] = b->slot[i].epoch;
     }
-    delete t;
+    apply_dev(b, blk, on_dev, epoch);
+    for (auto& sn : b->snap) sn.pending = false;  // older than this
+    b->applied = b->seq;
     return EK_OK;
 }
 
+// Snapshots whose chunk has finished, oldest first; never waits unless
+// `wait_one` (then for the older pending one).
+int reap_snaps(ek_batch* b, bool wait_one) {
+    for (int pass = 0; pass < 2; ++pass) {
+        int j = -1;
+        for (int q = 0; q < 2; ++q)
+            if (b->snap[q].pending && (j < 0 || b->snap[q].seq < b->snap[j].seq)) j = q;
+        if (j < 0) return EK_OK;
+        ek_batch::Snap& sn = b->snap[j];
+        hipError_t e = hipEventQuery(sn.ev);
+        if (e == hipErrorNotReady) {
+            if (!wait_one) return EK_OK;
+            BCHK(b, hipEventSynchronize(sn.ev));
+        } else {
+            BCHK(b, e);
+        }
+        wait_one = false;
+        if (sn.seq > b->applied) {
+            apply_dev(b, sn.host, sn.on_dev, sn.epoch);
+            b->applied = sn.seq;
+        }
+        sn.pending = false;
+    }
+    return EK_OK;
+}
+
+// Graphs replaced while launches of them may still be queued are destroyed
+// once an event recorded after their last launch has passed.
+void reap_graphs(ek_batch* b, bool all) {
+    for (size_t k = 0; k < b->retired.size();) {
+        auto& r = b->retired[k];
+        if (all || hipEventQuery(r.second) != hipErrorNotReady) {
+            (void)hipGraphExecDestroy(r.first);
+            (void)hipEventDestroy(r.second);
+            b->retired[k] = b->retired.back();
+            b->retired.pop_back();
+        } else {
+            ++k;
+        }
+    }
+}
+
+// Upload the host-owned table, merged into the live one in stream order:
+// no wait for the queued steps.
 int push_table(ek_batch* b) {
-    int r = pull_state(b);
-    if (r) return r;
     int n = 0;
     for (int i = 0; i < MAX_SLOTS; ++i)
         if (b->slot[i].used) n = i + 1;
     b->h.nsims = n;
     for (int k = 0; k < KK_N; ++k) b->h.start[k][0] = 0;
-    for (int i = 0; i < n; ++i) {
-        bool live = b->slot[i].used && b->h.active[i];
+    for (int i = 0; i < MAX_SLOTS; ++i) {
+        const bool live = i < n && b->slot[i].used && b->h.active[i];
+        b->h.keep[i] = b->slot[i].used && b->slot[i].on_device ? 1 : 0;
+        if (i >= n) continue;
         Grids<float> g = grids_of<float>(b->h.sims[i]);
         for (int k = 0; k < KK_N; ++k) b->h.start[k][i + 1] = b->h.start[k][i] + (live ? g.n[k] : 0);
     }
-    BCHK(b, hipMemcpyAsync(b->dtab, &b->h, sizeof(BatchTable), hipMemcpyHostToDevice, b->stream));
-    BCHK(b, hipStreamSynchronize(b->stream));
+    if (b->up_pending) {
+        BCHK(b, hipEventSynchronize(b->up_ev));  // the staging copy of the last upload is done
+        b->up_pending = false;
+    }
+    std::memcpy((void*)b->hup, (const void*)&b->h, sizeof(BatchTable));
+    BCHK(b, hipMemcpyAsync(b->dup, b->hup, sizeof(BatchTable), hipMemcpyHostToDevice, b->stream));
+    launch_batch_merge(b->dtab, b->dup, b->stream);
+    BCHK(b, hipGetLastError());
+    BCHK(b, hipEventRecord(b->up_ev, b->stream));
+    b->up_pending = true;
     for (int i = 0; i < n; ++i)
         if (b->slot[i].used) b->slot[i].on_device = true;
     b->dirty = false;
@@ -1249,11 +1335,21 @@ int ek_batch_create(size_t arena_bytes, int n_species, void* stream, void* arena
         }
         b->own_arena = true;
     }
+    // the live table, then the device staging of uploads, then the slots
+    const size_t tb = (sizeof(BatchTable) + SLOT_ALIGN - 1) & ~(SLOT_ALIGN - 1);
     b->dtab = (BatchTable*)b->arena;
-    size_t data0 = (sizeof(BatchTable) + SLOT_ALIGN - 1) & ~(SLOT_ALIGN - 1);
-    b->free_ranges[data0] = (arena_bytes - data0) & ~(SLOT_ALIGN - 1);
-    std::memset(&b->h, 0, sizeof(BatchTable));
-    if (hipMemcpy(b->dtab, &b->h, sizeof(BatchTable), hipMemcpyHostToDevice) != hipSuccess) {
+    b->dup = (BatchTable*)(b->arena + tb);
+    b->free_ranges[2 * tb] = (arena_bytes - 2 * tb) & ~(SLOT_ALIGN - 1);
+    std::memset((void*)&b->h, 0, sizeof(BatchTable));
+    bool ok = hipStreamCreateWithFlags(&b->admit_stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&b->up_ev, hipEventDisableTiming) == hipSuccess &&
+              hipHostMalloc((void**)&b->hup, sizeof(BatchTable), hipHostMallocDefault) == hipSuccess;
+    for (auto& sn : b->snap)
+        ok = ok && hipEventCreateWithFlags(&sn.ev, hipEventDisableTiming) == hipSuccess &&
+             hipHostMalloc((void**)&sn.host, BATCH_DEV_BYTES, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipMemcpy(b->dtab, &b->h, sizeof(BatchTable), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
         ek_batch_destroy(b);
         return EK_ERR_DEVICE;
     }
@@ -1279,7 +1375,7 @@ int batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n
     if (i == MAX_SLOTS) return EK_ERR_NO_SPACE;
     ek_params q = *p;
     q.max_particles = n_spheres > 0 ? n_spheres : 1;
-    q.stream = b->stream;
+    q.stream = b->admit_stream;  // built beside the running batch, which is not waited for
     q.arena = nullptr;
     q.arena_bytes = 0;
     size_t need = 0;
@@ -1316,7 +1412,9 @@ int batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n
     s.off = off;
     s.size = need;
     s.cells = c->N;
+    s.epoch += 1;
     b->h.sims[i] = c->sf;
+    b->h.cur[i] = c->sf.cur;
     b->h.sims[i].status = (uint32_t*)((unsigned char*)b->dtab + offsetof(BatchTable, status)) + i;
     b->h.sims[i].ticket = nullptr;  // the batch launches its pool kernel apart
     b->h.status[i] = 0;
@@ -1346,17 +1444,20 @@ int ek_batch_step(ek_batch* b, int k) {
         int r = push_table(b);
         if (r) return r;
     }
+    reap_graphs(b, false);
     // launches sized by work-item totals: capture again when the table's changed
     int items[KK_N];
     bool same = true;
-    for (int k = 0; k < KK_N; ++k) {
-        items[k] = b->h.start[k][b->h.nsims];
-        same = same && items[k] == b->graph_items[k];
+    for (int kk = 0; kk < KK_N; ++kk) {
+        items[kk] = b->h.start[kk][b->h.nsims];
+        same = same && items[kk] == b->graph_items[kk];
     }
     if (b->graph && !same) {
-        // the totals change only in push_table, which leaves the stream idle
-        BCHK(b, hipStreamSynchronize(b->stream));
-        (void)hipGraphExecDestroy(b->graph);
+        // launches of the old graph may still be queued: destroyed once passed
+        hipEvent_t ev = nullptr;
+        BCHK(b, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        BCHK(b, hipEventRecord(ev, b->stream));
+        b->retired.emplace_back(b->graph, ev);
         b->graph = nullptr;
     }
     if (!b->graph) {
@@ -1369,14 +1470,30 @@ int ek_batch_step(ek_batch* b, int k) {
         BCHK(b, e);
         for (int kk = 0; kk < KK_N; ++kk) b->graph_items[kk] = items[kk];
     }
+    if (k == 0) return EK_OK;
+    // at most two chunks ahead: the older one's snapshot is waited for (the
+    // device still has the newer one to run meanwhile)
+    if (b->snap[0].pending && b->snap[1].pending) {
+        int r = reap_snaps(b, true);
+        if (r) return r;
+    }
     for (int i = 0; i < k; ++i) BCHK(b, hipGraphLaunch(b->graph, b->stream));
+    ek_batch::Snap& sn = b->snap[b->snap[0].pending ? 1 : 0];
+    BCHK(b, hipMemcpyAsync(sn.host, b->dtab, BATCH_DEV_BYTES, hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipEventRecord(sn.ev, b->stream));
+    for (int i = 0; i < MAX_SLOTS; ++i) {
+        sn.on_dev[i] = b->slot[i].used && b->slot[i].on_device;
+        sn.epoch[i] = b->slot[i].epoch;
+    }
+    sn.seq = ++b->seq;
+    sn.pending = true;
     return EK_OK;
 }
 
 int ek_batch_poll(ek_batch* b, int* done_slots, int cap, int* n_done) {
     if (!b || !n_done || (cap > 0 && !done_slots)) return EK_ERR_INVALID_ARG;
     if (b->err) return b->err;
-    int r = pull_state(b);
+    int r = reap_snaps(b, false);
     if (r) return r;
     int n = 0;
     for (int i = 0; i < MAX_SLOTS; ++i) {
@@ -1393,6 +1510,12 @@ int ek_batch_poll(ek_batch* b, int* done_slots, int cap, int* n_done) {
     return EK_OK;
 }
 
+int ek_batch_wait(ek_batch* b) {
+    if (!b) return EK_ERR_INVALID_ARG;
+    if (b->err) return b->err;
+    return pull_state(b);
+}
+
 int ek_batch_get_fields(ek_batch* b, int slot, int field, void* host, size_t bytes) {
     if (!b || slot < 0 || slot >= MAX_SLOTS || !b->slot[slot].used) return EK_ERR_INVALID_ARG;
     if (b->err) return b->err;
@@ -1404,19 +1527,26 @@ int ek_batch_get_fields(ek_batch* b, int slot, int field, void* host, size_t byt
 int ek_batch_collect(ek_batch* b, int slot, ek_particle* out, int n, ek_diag* diag) {
     if (!b || slot < 0 || slot >= MAX_SLOTS || !b->slot[slot].used) return EK_ERR_INVALID_ARG;
     if (b->err) return b->err;
-    int r = pull_state(b);
-    if (r) return r;
     ek_batch::Slot& s = b->slot[slot];
+    // A reported slot stopped in a chunk that has finished: its state is
+    // final and no queued launch touches it.  Any other is waited for.
+    if (!s.reported) {
+        int r = pull_state(b);
+        if (r) return r;
+    }
     // a simulation whose kernels latched an error is retired with that error
     const int failed = s.on_device ? status_error(b->h.status[slot]) : EK_OK;
     if (!failed) {
+        int r = EK_OK;
         if (out && n > 0) r = ek_get_particles(s.ctx, out, n);
         if (!r && diag) r = ek_get_diagnostics(s.ctx, diag);
         if (r) return r;
     }
     ek_destroy(s.ctx);
     range_free(b, s.off, s.size);
+    const unsigned epoch = s.epoch;
     s = ek_batch::Slot();
+    s.epoch = epoch;
     b->h.active[slot] = 0;
     b->h.status[slot] = 0;
     b->dirty = true;
@@ -1443,6 +1573,14 @@ int ek_batch_destroy(ek_batch* b) {
     for (int i = 0; i < MAX_SLOTS; ++i)
         if (b->slot[i].used && b->slot[i].ctx) ek_destroy(b->slot[i].ctx);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    reap_graphs(b, true);
+    for (auto& sn : b->snap) {
+        if (sn.ev) (void)hipEventDestroy(sn.ev);
+        if (sn.host) (void)hipHostFree(sn.host);
+    }
+    if (b->up_ev) (void)hipEventDestroy(b->up_ev);
+    if (b->hup) (void)hipHostFree(b->hup);
+    if (b->admit_stream) (void)hipStreamDestroy(b->admit_stream);
     if (b->own_arena && b->arena) (void)hipFree(b->arena);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;

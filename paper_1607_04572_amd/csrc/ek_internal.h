@@ -259,14 +259,20 @@ inline Grids<T> grids_of(const S& s) {
 // ---------------------------------------------------------------------------
 constexpr int MAX_SLOTS = 64;
 struct BatchTable {
-    int nsims;                       // table entries in use (active or finishing)
+    // Device-owned: advanced by k_batch_flip.  This block alone goes back to
+    // the host after each chunk of steps (BATCH_DEV_BYTES from the start).
     int active[MAX_SLOTS];           // 1 while the slot still has steps to run
+    int cur[MAX_SLOTS];              // ping-pong index of each slot (sims[i].cur)
+    uint32_t status[MAX_SLOTS];      // each slot's device status word (its Sim's status points here)
     long long step[MAX_SLOTS];       // steps done
+    // Host-owned: uploaded and merged (k_batch_merge) when slots come or go.
+    int nsims;                       // table entries in use (active or finishing)
+    int keep[MAX_SLOTS];             // in an upload: 1 keeps the slot's device-owned entries
     long long target[MAX_SLOTS];     // steps requested
     int start[KK_N][MAX_SLOTS + 1];  // workgroup prefix sums per kernel kind
-    uint32_t status[MAX_SLOTS];      // each slot's device status word (its Sim's status points here)
     Sim<float> sims[MAX_SLOTS];
 };
+constexpr size_t BATCH_DEV_BYTES = offsetof(BatchTable, nsims);
 
 // Grid of a persistent batched kernel: as many workgroups as the current
 // device holds at once (every CU at the kernel's occupancy), so that all of
@@ -395,6 +401,7 @@ void launch_batch_fields(const BatchTable* tab, const int* items, int ns, hipStr
 void launch_batch_particle_forces(const BatchTable* tab, const int* items, hipStream_t st);
 void launch_batch_finish(const BatchTable* tab, hipStream_t st);
 void launch_batch_flip(BatchTable* tab, hipStream_t st);
+void launch_batch_merge(BatchTable* tab, const BatchTable* upload, hipStream_t st);
 void launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
 
 // Iterative Poisson solve with a relative permittivity field (ek_poisson_cg.hip):

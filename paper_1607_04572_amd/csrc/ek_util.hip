@@ -172,6 +172,7 @@ __global__ void k_batch_flip(BatchTable* tab) {
     int i = threadIdx.x;
     if (i >= tab->nsims || !tab->active[i]) return;
     tab->sims[i].cur ^= 1;
+    tab->cur[i] = tab->sims[i].cur;
     long long st = tab->step[i] + 1;
     tab->step[i] = st;
     if (st >= tab->target[i] || tab->status[i] != 0u) tab->active[i] = 0;
@@ -179,6 +180,31 @@ __global__ void k_batch_flip(BatchTable* tab) {
 
 void launch_batch_flip(BatchTable* tab, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_flip, dim3(1), dim3(MAX_SLOTS), 0, st, tab);
+}
+
+// An uploaded table into the live one, in stream order behind the steps
+// already queued: the host-owned part is taken whole; the device-owned
+// entries of a slot are taken from the upload only when it does not keep
+// them (a slot new since the last upload, or freed).
+__global__ void k_batch_merge(BatchTable* tab, const BatchTable* up) {
+    const uint32_t* src = (const uint32_t*)((const unsigned char*)up + BATCH_DEV_BYTES);
+    uint32_t* dst = (uint32_t*)((unsigned char*)tab + BATCH_DEV_BYTES);
+    constexpr int NW = (int)((sizeof(BatchTable) - BATCH_DEV_BYTES) / 4);
+    for (int w = threadIdx.x; w < NW; w += blockDim.x) dst[w] = src[w];
+    __syncthreads();
+    for (int i = threadIdx.x; i < MAX_SLOTS; i += blockDim.x) {
+        if (!up->keep[i]) {
+            tab->active[i] = up->active[i];
+            tab->cur[i] = up->cur[i];
+            tab->status[i] = up->status[i];
+            tab->step[i] = up->step[i];
+        }
+        tab->sims[i].cur = tab->cur[i];
+    }
+}
+
+void launch_batch_merge(BatchTable* tab, const BatchTable* upload, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_merge, dim3(1), dim3(256), 0, st, tab, upload);
 }
 
 }  // namespace ek

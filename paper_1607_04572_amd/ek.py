@@ -80,7 +80,7 @@ SYMBOLS = ["ek_query_footprint", "ek_create", "ek_add_sphere", "ek_set_static_bo
            "ek_destroy", "ek_strerror"]
 STAGES = ["move", "geometry", "boundary", "poisson", "forces", "ek", "lb", "finish"]
 BATCH_SYMBOLS = ["ek_batch_create", "ek_batch_admit", "ek_batch_admit_seeded", "ek_batch_step", "ek_batch_poll",
-                 "ek_batch_collect", "ek_batch_get_fields", "ek_batch_active", "ek_batch_destroy"]
+                 "ek_batch_wait", "ek_batch_collect", "ek_batch_get_fields", "ek_batch_active", "ek_batch_destroy"]
 
 _LIB = None
 
@@ -123,6 +123,7 @@ def lib():
                                             C.c_longlong, P(C.c_int)]
         L.ek_batch_step.argtypes = [vp, C.c_int]
         L.ek_batch_poll.argtypes = [vp, P(C.c_int), C.c_int, P(C.c_int)]
+        L.ek_batch_wait.argtypes = [vp]
         L.ek_batch_collect.argtypes = [vp, C.c_int, P(ek_particle), C.c_int, P(ek_diag)]
         L.ek_batch_get_fields.argtypes = [vp, C.c_int, C.c_int, vp, C.c_size_t]
         L.ek_batch_active.argtypes = [vp, P(C.c_int), P(C.c_longlong)]
@@ -319,6 +320,10 @@ def ek_batch_step(b, k: int):
     _check(lib().ek_batch_step(b, int(k)), "ek_batch_step")
 
 
+def ek_batch_wait(b):
+    _check(lib().ek_batch_wait(b), "ek_batch_wait")
+
+
 def ek_batch_poll(b, cap: int = 64) -> list:
     out = (C.c_int * cap)()
     n = C.c_int(0)
@@ -393,7 +398,11 @@ class EkBatch:
     def step(self, k: int):
         ek_batch_step(self.h, k)
 
-    def poll(self) -> list:
+    def poll(self, wait: bool = False) -> list:
+        """Slots done as of the chunks that have finished (wait: of every
+        queued chunk)."""
+        if wait:
+            ek_batch_wait(self.h)
         return ek_batch_poll(self.h)
 
     def field(self, slot: int, name: str) -> np.ndarray:

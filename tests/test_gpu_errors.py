@@ -121,7 +121,7 @@ def test_batch_retires_a_failed_request():
     done = set()
     for _ in range(10):
         b.step(4)
-        done |= set(b.poll())
+        done |= set(b.poll(wait=True))
         if s_ok in done:
             break
     assert s_bad in done and s_ok in done

@@ -93,11 +93,11 @@ def test_admission_by_footprint():
         b.admit(C, n_steps=3)
     assert e.value.code == -6
     b.step(3)
-    assert b.poll() == [s1]
+    assert b.poll(wait=True) == [s1]
     b.collect(s1)
     s2 = b.admit(C, n_steps=2)
     b.step(2)
-    assert b.poll() == [s2]
+    assert b.poll(wait=True) == [s2]
     b.collect(s2)
     b.close()
 
