@@ -167,13 +167,17 @@ def copy_probe(mib: int, reps: int = 10) -> dict:
     return {"bytes_per_launch": 2 * n, "ms": ms, "GBps": 2 * n / (ms * 1e-3) / 1e9}
 
 
-def cpu_baseline(w, budget_s: float = 12.0) -> dict:
+def cpu_baseline(w, budget_s: float = 12.0, threads: int = 0) -> dict:
     """The FP64 CPU oracle on a bounded sample of the same workload: full
-    steps until about budget_s seconds have passed (2 to 8 steps)."""
+    steps until about budget_s seconds have passed (2 to 8 steps), on
+    `threads` OpenMP threads (0: as many as the environment gives)."""
     import ctypes
 
     from oracle import oracle as O
     from paper_1607_04572_amd import workloads as W
+
+    if threads > 0:
+        O.lib().or_set_num_threads(ctypes.c_int(threads))
 
     p = O.make_params(*w.shape, w.nu, w.kT, w.lambda_B, w.E, [(s.D, s.z) for s in w.species],
                       partial_volume=w.scheme == "pv", charge_mode=1 if w.charge == "uniform" else 0,
@@ -199,12 +203,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c3", choices=["c0", "c1", "c2", "c3"])
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-boundary-cost", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="threads of the CPU oracle (0: all it is given)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run the plain copy kernel on buffers of this size (counter calibration)")
@@ -219,32 +224,34 @@ def main():
     w32 = W.CONFIGS[args.workload]("fp32") if args.workload != "c0" else W.c0()
     dt, stages, diag = run_gpu(w32, args.steps, args.warmup, args.profile_steps)
     mlups = w32.cells * args.steps / dt / 1e6
+    fp64 = w32.precision == "fp64"  # the 32^3 prescribed-sphere case: FP64 plain, EK and LB fused
+    elem = 8 if fp64 else 4
     kern = {}
-    for st in ("lb", "ek", "poisson"):
-        b = algorithmic_bytes(st, w32, 4) * w32.cells
+    for st in (("ek", "poisson") if fp64 else ("lb", "ek", "poisson")):
+        bpc = algorithmic_bytes(st, w32, elem, fused=fp64 and st == "ek")
         ms = stages[st]
-        kern[st] = {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9, "bytes_per_cell": algorithmic_bytes(st, w32, 4)}
-    fk = kern["lb"]
+        kern[st] = {"ms": ms, "GBps": bpc * w32.cells / (ms * 1e-3) / 1e9, "bytes_per_cell": bpc}
+    fk = kern["ek" if fp64 else "lb"]
     from paper_1607_04572_amd import counters
-    meas = counters.stored_traffic()
+    meas = None if fp64 else counters.stored_traffic()
     lb_bytes = fk["bytes_per_cell"] * w32.cells
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": w32.precision, "data": "synthetic",
         "config": {"workload": w32.name, "cells": w32.cells, "shape": list(w32.shape),
                    "spheres": len(w32.spheres), "species": len(w32.species),
-                   "storage": "fp32 deviations (fp64 particles, sums, redistribution)",
-                   "scheme": "partial volume", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_lb (stream/collide)",
+                   "storage": "fp64 plain" if fp64 else "fp32 deviations (fp64 particles, sums, redistribution)",
+                   "scheme": "partial volume" if w32.scheme == "pv" else "simple", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_ek (EK + LB fused)" if fp64 else "k_lb (stream/collide)",
                      "achieved": fk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": fk["GBps"] / HBM_PEAK_GBS,
                      "traffic": meas["traffic_bytes_per_launch"] if meas else None,
                      "traffic_over_algorithmic": meas["traffic_bytes_per_launch"] / lb_bytes if meas else None,
                      "bytes_per_launch": lb_bytes, "launch_ms": fk["ms"]},
         # the state floor: populations and densities read and written once, the potential once each way
-        "effective": {"bytes_per_lup": state_bytes(w32, 4), "GBps": state_bytes(w32, 4) * mlups * 1e6 / 1e9,
-                      "frac": state_bytes(w32, 4) * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
+        "effective": {"bytes_per_lup": state_bytes(w32, elem), "GBps": state_bytes(w32, elem) * mlups * 1e6 / 1e9,
+                      "frac": state_bytes(w32, elem) * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
         "kernels": {"stage_ms": stages, **{k: v for k, v in kern.items()},
                     "particle_frac": sum(stages[k] for k in PARTICLE_STAGES) / sum(stages.values())},
         "diagnostics": {"species_total": [float(x) for x in diag["species_total"][:len(w32.species)]],
@@ -252,7 +259,7 @@ def main():
     }
     if not args.no_boundary_cost:
         out["boundary_cost"] = boundary_cost(w32, min(args.steps, 100), args.warmup)
-    if not args.no_fp64:
+    if not args.no_fp64 and not fp64:
         w64 = w32.replace(precision="fp64", name=w32.name.replace("fp32", "fp64"))
         steps64 = max(10, args.steps // 2)
         dt64, st64, _ = run_gpu(w64, steps64, args.warmup, args.profile_steps)
@@ -268,7 +275,7 @@ def main():
     if args.copy_probe_mib:
         out["copy_probe"] = copy_probe(args.copy_probe_mib)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w32)
+        out["cpu_baseline"] = cpu_baseline(w32, threads=args.cpu_threads)
     print(json.dumps(out), flush=True)
 
 

@@ -23,8 +23,12 @@
 #include <stdlib.h>
 #include <string.h>
 
-/* Number of OpenMP threads the oracle's parallel loops use. */
+/* Number of OpenMP threads the oracle's parallel loops use, and a setter
+ * (timing with a chosen number of threads; n < 1 is ignored). */
 int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_num_threads(int n) {
+    if (n >= 1) omp_set_num_threads(n);
+}
 
 /* ---------------------------------------------------------------------------
  * D3Q19 velocity set (Sec. III.A: rest vector, 6 face and 12 edge neighbours).
