@@ -38,7 +38,7 @@ double d_max() {
 
 struct Layout {
     size_t f, rho, u, fext, phi, rhob, psi, flag, owner, owner_prev, psi_owner, spec, tw, k2, parts, scratch,
-        partial, diag, status, ticket, state_end, total;
+        partial, diag, status, state_end, total;
 };
 
 Layout make_layout(const ek_params* p, size_t ts) {
@@ -71,7 +71,6 @@ Layout make_layout(const ek_params* p, size_t ts) {
     L.partial = take((size_t)PART_KINDS * mp * MAX_CHUNKS * PSTRIDE * sizeof(double));
     L.diag = take(64 * sizeof(double));
     L.status = take(sizeof(uint32_t));
-    L.ticket = take(sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -228,7 +227,6 @@ void setup_sim(ek_ctx* c, Sim<T>& s) {
     s.k2[2] = k2 + p->nx + p->ny;
     s.parts = (PState*)(A + L.parts);
     s.status = (uint32_t*)(A + L.status);
-    s.ticket = (uint32_t*)(A + L.ticket);
     s.scratch = (double*)(A + L.scratch);
     s.partial = (double*)(A + L.partial);
     s.box_max = 0;
@@ -258,7 +256,6 @@ int init_fields(ek_ctx* c, Sim<T>& s) {
     fill<uint16_t>(s.owner_prev, N, NO_OWNER, st);
     fill<uint16_t>(s.psi_owner, N, NO_OWNER, st);
     HIPCHK(c, hipMemsetAsync(s.status, 0, sizeof(uint32_t), st));
-    HIPCHK(c, hipMemsetAsync(s.ticket, 0, sizeof(uint32_t), st));
     // FFT tables in FP64 on the host, rounded once to T
     int n[3] = {p->nx, p->ny, p->nz};
     std::vector<T> tw, k2;
@@ -1416,7 +1413,6 @@ int batch_admit(ek_batch* b, const ek_params* p, const ek_sphere* spheres, int n
     b->h.sims[i] = c->sf;
     b->h.cur[i] = c->sf.cur;
     b->h.sims[i].status = (uint32_t*)((unsigned char*)b->dtab + offsetof(BatchTable, status)) + i;
-    b->h.sims[i].ticket = nullptr;  // the batch launches its pool kernel apart
     b->h.status[i] = 0;
     b->h.step[i] = 0;
     b->h.target[i] = n_steps;

@@ -140,7 +140,6 @@ struct Sim {
     T* k2[3];                 // 2 - 2 cos(2 pi m / n) per axis
     PState* parts;
     uint32_t* status;         // device status word (ST_* bits), zero while the state is sound
-    uint32_t* ticket;         // workgroups of k_boundary_post done this step (null: pool launched apart)
     double* scratch;          // reductions
     double* partial;          // per-(particle, chunk) partial sums of the particle kernels
     int box_max;              // bound on cells of one particle box

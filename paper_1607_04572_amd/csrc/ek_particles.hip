@@ -778,28 +778,19 @@ __device__ __forceinline__ void boundary_post_body(const Sim<T>& s, int bx_, int
             s.rhob[c] = (T)qb;
         }
     }
-    if (!s.ticket) return;
-    // The last workgroup to finish runs the global pool (every particle
-    // record is final then; the pool writes only stable cells, which no
-    // workgroup here writes), which exits at once when nothing was pooled:
-    // no launch of its own in the usual case.  Release of this workgroup's
-    // writes, then its ticket (device-scope atomic).
-    __shared__ int last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last = atomicAdd(s.ticket, 1u) == gridDim.x * gridDim.y - 1u;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();  // acquire the other workgroups' records
-    if (threadIdx.x == 0) *s.ticket = 0u;  // every workgroup has taken its ticket
-    pool_body<T>(s, 0, 0, 1);
 }
 
 template <typename T>
 __global__ __launch_bounds__(PT) void k_boundary_post(Sim<T> s) {
     boundary_post_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// (Run by the last workgroup of k_boundary_post instead, behind a
+// device-scope release fence in every workgroup, this cost more than its own
+// launch: each such fence writes the L2 back.)
+template <typename T>
+__global__ __launch_bounds__(PT) void k_pool(Sim<T> s) {
+    pool_body<T>(s, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 
@@ -1137,7 +1128,8 @@ template <typename T>
 void launch_boundary(const Sim<T>& s, hipStream_t st) {
     if (s.np == 0) return;
     hipLaunchKernelGGL(k_boundary<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
-    hipLaunchKernelGGL(k_boundary_post<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);  // and the pool
+    hipLaunchKernelGGL(k_boundary_post<T>, dim3(s.nchunk, s.np), dim3(PT), 0, st, s);
+    hipLaunchKernelGGL(k_pool<T>, dim3(POOL_BLOCKS), dim3(PT), 0, st, s);
 }
 
 template <typename T>
