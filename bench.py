@@ -198,6 +198,11 @@ def cpu_baseline(w, budget_s: float = 12.0, threads: int = 0) -> dict:
             "sample": f"{n} full steps of {w.name} ({w.cells} cells, FP64 oracle) after one untimed, {dt:.1f} s"}
 
 
+def progress(msg: str):
+    """One line per finished stage on stderr (a long run shows it is alive)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +229,7 @@ def main():
     w32 = W.CONFIGS[args.workload]("fp32") if args.workload != "c0" else W.c0()
     dt, stages, diag = run_gpu(w32, args.steps, args.warmup, args.profile_steps)
     mlups = w32.cells * args.steps / dt / 1e6
+    progress(f"{w32.name}: {mlups:.0f} MLUPS")
     fp64 = w32.precision == "fp64"  # the 32^3 prescribed-sphere case: FP64 plain, EK and LB fused
     elem = 8 if fp64 else 4
     kern = {}
@@ -259,6 +265,7 @@ def main():
     }
     if not args.no_boundary_cost:
         out["boundary_cost"] = boundary_cost(w32, min(args.steps, 100), args.warmup)
+        progress("boundary cost done")
     if not args.no_fp64 and not fp64:
         w64 = w32.replace(precision="fp64", name=w32.name.replace("fp32", "fp64"))
         steps64 = max(10, args.steps // 2)
@@ -269,13 +276,16 @@ def main():
                              "steps": steps64, "stage_ms": st64,
                              "fused_ek_lb_GBps": b64 / (st64["ek"] * 1e-3) / 1e9}
         out["fp32_over_fp64"] = mlups / m64
+        progress(f"fp64: {m64:.0f} MLUPS")
     if not args.no_serve:
         from paper_1607_04572_amd import serve
         out["serve"] = serve.serve_benchmark(n_requests=args.serve_requests, extra_loads=(2.0,))
+        progress("serve loop done")
     if args.copy_probe_mib:
         out["copy_probe"] = copy_probe(args.copy_probe_mib)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w32, threads=args.cpu_threads)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 
