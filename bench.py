@@ -19,6 +19,9 @@ One JSON line is printed with the contract fields plus:
                    null once the kernel's sources differ from the measured ones;
   cpu_baseline  -- the FP64 CPU oracle timed on a few full steps (about 12 s)
                    of the same workload;
+  step_hbm      -- the whole FP32 step: HBM bytes of its kernels from the same
+                   counter passes / the step time, against 8 TB/s (null once
+                   any kernel source differs from the measured one);
   effective     -- the state floor (populations and densities read and
                    written once, potential once each way) x MLUPS, vs 8 TB/s;
   kernels       -- per-stage mean times and algorithmic-byte bandwidths;
@@ -258,6 +261,11 @@ def main():
         # the state floor: populations and densities read and written once, the potential once each way
         "effective": {"bytes_per_lup": state_bytes(w32, elem), "GBps": state_bytes(w32, elem) * mlups * 1e6 / 1e9,
                       "frac": state_bytes(w32, elem) * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
+        # the whole step from the stored counter passes: HBM bytes of its kernels / the step time
+        "step_hbm": None if fp64 or counters.stored_step_bytes() is None else {
+            "bytes_per_step": counters.stored_step_bytes(),
+            "GBps": counters.stored_step_bytes() / (dt / args.steps) / 1e9,
+            "frac": counters.stored_step_bytes() / (dt / args.steps) / 1e9 / HBM_PEAK_GBS},
         "kernels": {"stage_ms": stages, **{k: v for k, v in kern.items()},
                     "particle_frac": sum(stages[k] for k in PARTICLE_STAGES) / sum(stages.values())},
         "diagnostics": {"species_total": [float(x) for x in diag["species_total"][:len(w32.species)]],

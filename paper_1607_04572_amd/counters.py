@@ -27,14 +27,23 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 STORE = os.path.join(HERE, "counters.json")
 KERNEL = "k_lb<float, true>"
 SOURCES = ["csrc/ek_lb.h", "csrc/ek_lb.hip", "csrc/ek_internal.h"]
+# Kernels of one FP32 step (k_move runs apart only at the start of a graph-replayed chain of steps, with
+# no measurable traffic), for the step-level figure; it holds while no kernel source has changed.
+STEP_KERNELS = ["k_lb<float", "k_ek32<", "k_fft_", "k_geometry<float", "k_boundary<float", "k_boundary_post<float",
+                "k_pool<float", "k_particle_forces<float", "k_finish<float"]
 
 
-def source_hash() -> str:
+def source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for s in SOURCES:
+    for s in sources or SOURCES:
         with open(os.path.join(HERE, s), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def all_sources() -> list:
+    d = os.path.join(HERE, "csrc")
+    return sorted("csrc/" + f for f in os.listdir(d) if f.endswith((".h", ".hip", ".cpp")))
 
 
 def per_dispatch(db: str, counter: str) -> dict:
@@ -71,10 +80,22 @@ def main(fetch_db: str, write_db: str, copy_mib: int) -> dict:
         "traffic_bytes_per_launch": (f_lb * f_scale + w_lb * w_scale) * 1024.0,
         "read_bytes_per_launch": f_lb * f_scale * 1024.0, "write_bytes_per_launch": w_lb * w_scale * 1024.0,
         "all_kernels_fetch_kib": fetch, "all_kernels_write_kib": write,
+        "step_bytes": sum(fetch[k] * f_scale * 1024.0 + write.get(k, 0.0) * w_scale * 1024.0
+                          for k in fetch if any(s in k for s in STEP_KERNELS)),
+        "all_sources_sha256": source_hash(all_sources()),
     }
     with open(STORE, "w") as f:
         json.dump(out, f, indent=1)
     return out
+
+
+def stored_step_bytes() -> float | None:
+    """HBM bytes of one FP32 step from the stored passes, if no kernel source has changed since."""
+    if not os.path.exists(STORE):
+        return None
+    with open(STORE) as f:
+        d = json.load(f)
+    return d.get("step_bytes") if d.get("all_sources_sha256") == source_hash(all_sources()) else None
 
 
 def stored_traffic() -> dict | None:
