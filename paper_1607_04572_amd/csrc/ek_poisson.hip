@@ -555,6 +555,124 @@ __device__ __forceinline__ void store_tile_c(const cpx<T>* a, int ld, cpx<T>* g,
 // ---------------------------------------------------------------------------
 // Pass Y (forward or inverse): pencils along y, TX consecutive kx per group.
 // ---------------------------------------------------------------------------
+// Stages of the y and z passes that move data straight between HBM and registers
+// (compile-time length N and full groups of PC columns).  The same butterflies,
+// twiddles (and Green's factors) as the staged pass in the same order, so the
+// results are bit-identical; what goes is the staging of the group in LDS
+// before the first stage, the copy out of LDS after the last stage and, in the
+// z pass, the Green's pass over LDS (LDS round trips and their barriers).  Their
+// lanes take the group's columns fastest (b = j PC + column), so that the HBM
+// accesses of a wavefront are whole rows of PC columns; pencils an odd number
+// of elements apart keep the LDS side free of bank conflicts.
+// ---------------------------------------------------------------------------
+constexpr int radix_rt(int m) { return m % 8 == 0 ? 8 : (m % 4 == 0 ? 4 : (m % 2 == 0 ? 2 : 3)); }
+// Stride NS of the last stage of the radix plan of N.
+constexpr int last_stride(int n) {
+    int ns = 1;
+    while (ns * radix_rt(n / ns) < n) ns *= radix_rt(n / ns);
+    return ns;
+}
+template <int N, int PC>
+constexpr bool direct_ok() {
+    return PC > 0 && N > 0 && (N & (N - 1)) == 0 && N >= 64 && (PC * (N / 8)) % FT == 0 &&
+           (PC * (N / radix_rt(N / last_stride(N)))) % FT == 0 && (FT % PC) == 0;
+}
+
+// First stage (stride 1, radix 8) of a transform, its inputs read from HBM:
+// pencil i of the group is g[z * rs + i], z = 0 .. N-1.
+template <typename T, int N, int PC, bool INV>
+__device__ __forceinline__ void stage_first_from_hbm(cpx<T>* a, int ld, const cpx<T>* __restrict__ g, long rs) {
+    constexpr int R = radix_of<N>(), nR = N / R, NB = PC * nR / FT;
+    static_assert(R == 8 && PC * nR == NB * FT, "group shape");
+    cpx<T> v[NB][R];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int b = threadIdx.x + q * FT, pen = b % PC, j = b / PC;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = gld(g + (long)(j + r * nR) * rs + pen);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int b = threadIdx.x + q * FT, pen = b % PC, j = b / PC;
+        dft_small<T, R, INV>(v[q]);
+        cpx<T>* o = a + pen * ld + pad(j * R);  // stride 1: outputs j R + r
+#pragma unroll
+        for (int r = 0; r < R; ++r) o[r] = v[q][r];
+    }
+    __syncthreads();
+}
+
+// First stage (stride 1, radix 8) of the inverse transform with the Green's
+// factor applied to each input as it is read (input m of pencil i is the
+// mode (kx0 + i, ky, m)).
+template <typename T, int N, int PC, typename G>
+__device__ __forceinline__ void stage_first_green(cpx<T>* a, int ld, G&& green) {
+    constexpr int R = radix_of<N>(), nR = N / R, NB = PC * nR / FT;
+    static_assert(R == 8 && PC * nR == NB * FT, "group shape");
+    cpx<T> v[NB][R];
+    int dst[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int b = threadIdx.x + q * FT, pen = b / nR, j = b % nR;
+        const cpx<T>* src = a + pen * ld + pad(j);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const cpx<T> x = src[r * (nR + nR / 8)];  // element j + r nR
+            const T gf = green(pen, j + r * nR);
+            v[q][r] = mk<T>(x.x * gf, x.y * gf);
+        }
+        dst[q] = pen * ld + pad(j * R);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        dft_small<T, R, true>(v[q]);
+        cpx<T>* o = a + dst[q];
+#pragma unroll
+        for (int r = 0; r < R; ++r) o[r] = v[q][r];
+    }
+    __syncthreads();
+}
+
+// The stages of stride NS up to (not including) the last one.
+template <typename T, int N, bool INV, int PC, int NS>
+__device__ __forceinline__ void stages_mid(cpx<T>* a, int ld, const cpx<T>* __restrict__ tw) {
+    if constexpr (NS < last_stride(N)) {
+        constexpr int R = radix_of<N / NS>();
+        stage_c<T, N, R, NS, INV, PC>(a, PC, ld, tw);
+        stages_mid<T, N, INV, PC, NS * R>(a, ld, tw);
+    }
+}
+
+// Last stage (stride NS, NS R = N) of a transform, its outputs written to
+// HBM: output z = k + r NS of pencil i at g[z * rs + i].
+template <typename T, int N, int PC, bool INV>
+__device__ __forceinline__ void stage_last_to_hbm(const cpx<T>* a, int ld, const cpx<T>* __restrict__ tw,
+                                                  cpx<T>* __restrict__ g, long rs) {
+    constexpr int NS = last_stride(N), R = N / NS, nR = N / R, NB = PC * nR / FT;
+    static_assert(PC * nR == NB * FT && nR == NS, "group shape");
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int b = threadIdx.x + q * FT, pen = b % PC, k = b / PC;  // k = j: the stage's span is 1
+        const cpx<T>* src = a + pen * ld;
+        cpx<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cpx<T> x = src[pad(k + r * nR)];
+            if (r > 0) {
+                cpx<T> w = tw[k * r];
+                if (INV) w.y = -w.y;
+                x = cmul<T>(x, w);
+            }
+            v[r] = x;
+        }
+        dft_small<T, R, INV>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) gst(g + (long)(k + r * NS) * rs + pen, v[r]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 template <typename T, bool INV, int NC, int TCC>
 __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int TX) {
     extern __shared__ unsigned char smem_raw[];
@@ -569,6 +687,12 @@ __device__ __forceinline__ void fft_y_body(const Sim<T>& s, int bx_, int TX) {
     cpx<T>* S = reinterpret_cast<cpx<T>*>(s.spec) + (long)z * n * s.nxs;
     const FDiv dtc(TCC > 0 ? 1 : TC);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[1], n);
+    if constexpr (direct_ok<NC, TCC>()) {
+        stage_first_from_hbm<T, NC, TCC, INV>(a, ld, S + kx0, s.nxs);
+        stages_mid<T, NC, INV, TCC, radix_of<NC>()>(a, ld, tw);
+        stage_last_to_hbm<T, NC, TCC, INV>(a, ld, tw, S + kx0, s.nxs);
+        return;
+    }
     if constexpr (tile_c_ok<TCC, NC>()) load_tile_c<T, TCC, NC>(a, ld, S + kx0, s.nxs);
     else load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int y, int i) { return gld(S + (long)y * s.nxs + kx0 + i); });
     __syncthreads();
@@ -603,12 +727,33 @@ __device__ __forceinline__ void fft_z_green_body(const Sim<T>& s, int bx_, int T
     const FDiv dtc(TCC > 0 ? 1 : TC), dn(NC > 0 ? 1 : n);
     const cpx<T>* tw = stage_twiddles<T>(a, TX * ld, s.tw[2], n);
     cpx<T>* G = S + (long)ky * s.nxs + kx0;  // row z of the group at G + z zstride
+    const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
+    const T K2y = gld(s.k2[1] + ky);
+    if constexpr (direct_ok<NC, TCC>()) {
+        // Green's factor of mode (kx0 + i, ky, kz), as in the staged form below
+        auto green = [&](int i, int kz) -> T {
+            const int kx = kx0 + i;
+            const T K2 = gld(s.k2[0] + kx) + K2y + gld(s.k2[2] + kz);
+            T g;
+            if constexpr (sizeof(T) == 4) g = scale * __builtin_amdgcn_rcpf(K2);
+            else g = scale / K2;
+            return (kx == 0 && ky == 0 && kz == 0) ? (T)0 : g;
+        };
+        stage_first_from_hbm<T, NC, TCC, false>(a, ld, G, zstride);
+        stages_mid<T, NC, false, TCC, radix_of<NC>()>(a, ld, tw);
+        {
+            constexpr int NSL = last_stride(NC);
+            stage_c<T, NC, NC / NSL, NSL, false, TCC>(a, TCC, ld, tw);  // the forward transform's last stage
+        }
+        stage_first_green<T, NC, TCC>(a, ld, green);
+        stages_mid<T, NC, true, TCC, radix_of<NC>()>(a, ld, tw);
+        stage_last_to_hbm<T, NC, TCC, true>(a, ld, tw, G, zstride);
+        return;
+    }
     if constexpr (tile_c_ok<TCC, NC>()) load_tile_c<T, TCC, NC>(a, ld, G, zstride);
     else load_tile<T, TCC>(a, ld, TC, n, dtc, [&](int z, int i) { return gld(G + z * zstride + i); });
     __syncthreads();
     fft_n<T, false, NC, TCC>(a, n, TC, ld, tw);
-    const T scale = (T)(4.0 * 3.14159265358979323846 * s.lambda_B / (double)s.N);
-    const T K2y = gld(s.k2[1] + ky);
 #pragma unroll
     for (int it = 0; it < FE; ++it) {
         const int t = threadIdx.x + it * FT;
