@@ -537,6 +537,24 @@ __device__ __forceinline__ double rho_abs(const Sim<T>& s, const T* r, int k, lo
 // Also counts the particle's boundary cells (n_b), collects the solute of
 // covered cells that have no stable-fluid neighbour at all (global pool), and
 // performs the solute expel for the stable cells of the box (expel_cell).
+// Can a cell have a newly covered neighbour?  A covered cell is claimed by a
+// particle q, so its centre lies within R_q of q's centre, and a neighbour's
+// centre within R_q + sqrt 3; q's box then meets this box, so q is on the
+// list.  Cells farther than R_q + 2 from every listed centre skip the load of
+// their 26 neighbour flags (most of a box).
+template <typename T>
+__device__ __forceinline__ bool near_a_surface(const Sim<T>& s, const NbrList& L, int x, int y, int z) {
+    const int n = nbr_count(L, s.np);
+    for (int j = 0; j < n; ++j) {
+        const NbrRec q = nbr_rec(s, L, j);
+        double d[3];
+        cell_disp(s, x, y, z, q.x, d);
+        const double rr = q.R + 2.0;
+        if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] <= rr * rr) return true;
+    }
+    return false;
+}
+
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_, int gx_) {
@@ -559,7 +577,8 @@ __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_,
         const uint16_t own = s.owner[c];
         if ((fl & F_CUR) && own == p) acc[6 + MAXS + 3] += 1.0;  // n_b
         if ((fl & (F_CUR | F_PREV)) && !(fl & F_WALL) && box_owner_is(s, L, p, x, y, z)) acc[6 + MAXS + 4] += 1.0;
-        if (stable(fl) && box_owner_is(s, L, p, x, y, z)) expel_cell(s, s.rho[s.cur], x, y, z, c);
+        if (stable(fl) && box_owner_is(s, L, p, x, y, z) && near_a_surface(s, L, x, y, z))
+            expel_cell(s, s.rho[s.cur], x, y, z, c);
         if (covered(fl) && own == p) {
             double pf[3] = {0.0, 0.0, 0.0};
             sfor<19>([&](auto I) {
