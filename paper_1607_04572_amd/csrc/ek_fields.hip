@@ -785,12 +785,12 @@ void launch_fields(const Sim<T>& s, hipStream_t st, hipEvent_t mid) {
 constexpr int BATCH_FIELD_BLOCKS = 2048;
 constexpr bool FLAT_EK = false;
 
-// Up to two species: four waves per SIMD (the batch loop's bookkeeping puts the
-// kernel at 134 VGPRs, three waves, otherwise; four waves with a few spilled
-// registers serve about 3.5 % more cells per second).
+// (Four waves per SIMD with a few registers spilled served about 3.5 % more
+// cells per second before the staging was pipelined; with the loads of the
+// next plane in flight, a spill reload waits for them, so the compiler's
+// choice stands.)
 template <int NS>
-__global__ __launch_bounds__(EKTile<float>::TXW* EKTile<float>::TYW)
-__attribute__((amdgpu_waves_per_eu(NS <= 2 ? 4 : 2))) void kb_ek(const BatchTable* __restrict__ tab) {
+__global__ __launch_bounds__(EKTile<float>::TXW* EKTile<float>::TYW) void kb_ek(const BatchTable* __restrict__ tab) {
     constexpr int TXW = EKTile<float>::TXW, TYW = EKTile<float>::TYW, ZC = EKTile<float>::ZC;
     batch_run<KK_EK, FLAT_EK>(tab, [](const Sim<float>& s, int b) {
         const int gx = (s.nx + TXW - 1) / TXW, gy = (s.ny + TYW - 1) / TYW;
