@@ -449,6 +449,23 @@ __device__ __forceinline__ unsigned lb_bmask_lds(const EKShared<T, NS, TXW, TYW>
     return m;
 }
 
+// Block-wide OR of a predicate through one LDS word per wave.  (The runtime's
+// __syncthreads_or reads the block size from memory and so waits for every
+// outstanding vector memory operation, the stores of the plane just finished
+// and the loads of the plane being fetched among them.)  w must not be
+// written again before every wave has read it: callers alternate between
+// arrays separated by other barriers.
+template <int NW>
+__device__ __forceinline__ bool block_any(int (&w)[NW], bool p) {
+    const int wave_any = __any(p);
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = wave_any;
+    __syncthreads();
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r |= w[i];
+    return r != 0;
+}
+
 // Grid: tiles of TXW x TYW cells in x-y times z-chunks of ZC planes, flattened
 // and mapped with xcd_tile; each workgroup marches its ZC planes.
 // FUSE: the cell's LB stream/collide follows its EK update in the same thread,
@@ -462,7 +479,9 @@ __device__ __forceinline__ unsigned lb_bmask_lds(const EKShared<T, NS, TXW, TYW>
 template <typename T, bool DEV, int NS, int TXW, int TYW, bool FUSE, bool PREFETCH = true>
 __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int gx_, int ZC, int gx, int gy, int ntiles) {
     using SH = EKShared<T, NS, TXW, TYW>;
+    constexpr int NW = TXW * TYW / 64;
     __shared__ SH sh;
+    __shared__ int wany[3][NW];  // per slot, for block_any
     const int tile = xcd_tile(bx_, ntiles);
     const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
     const int x0 = bx * TXW, y0 = by * TYW, zbeg = bz * ZC;
@@ -474,7 +493,7 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
     {
         bool d0 = ek_load_plane<T, NS, TXW, TYW>(s, sh, (zbeg + 2) % 3, pm, zbeg - 1, rin);
         bool d1 = ek_load_plane<T, NS, TXW, TYW>(s, sh, zbeg % 3, pm, zbeg, rin);
-        int a0 = __syncthreads_or(d0), a1 = __syncthreads_or(d1);
+        const int a0 = block_any<NW>(wany[(zbeg + 2) % 3], d0), a1 = block_any<NW>(wany[zbeg % 3], d1);
         if (threadIdx.x == 0) {
             sh.dirty[(zbeg + 2) % 3] = a0;
             sh.dirty[zbeg % 3] = a1;
@@ -494,7 +513,7 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
             if (valid && !wall) lb_pull(s, Nbr(x, y, z, s.nx, s.ny, s.nz), fi);
         }
         bool dn = ek_load_plane<T, NS, TXW, TYW>(s, sh, sp, pm, z + 1, rin);
-        int an = __syncthreads_or(dn);
+        const int an = block_any<NW>(wany[sp], dn);
         if (threadIdx.x == 0) sh.dirty[sp] = an;
         __syncthreads();
         const bool clean = !(sh.dirty[0] | sh.dirty[1] | sh.dirty[2]);
@@ -607,22 +626,6 @@ __device__ __forceinline__ bool plane_commit(EKShared<float, NS, TXW, TYW>& sh, 
     return dirty;
 }
 
-// Block-wide OR of a predicate through one LDS word per wave.  (The runtime's
-// __syncthreads_or reads the block size from memory and so waits for every
-// outstanding vector memory operation, the stores of the plane just finished
-// and the loads of the plane being fetched among them.)  w must not be
-// written again before every wave has read it: callers alternate between
-// arrays separated by other barriers.
-template <int NW>
-__device__ __forceinline__ bool block_any(int (&w)[NW], bool p) {
-    const int wave_any = __any(p);
-    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = wave_any;
-    __syncthreads();
-    int r = 0;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) r |= w[i];
-    return r != 0;
-}
 
 template <int NS, int TXW, int TYW>
 __device__ __forceinline__ void ek_body_pipe(const Sim<float>& s, int bx_, int ZC, int gx, int gy, int ntiles) {
