@@ -574,30 +574,34 @@ constexpr int last_stride(int n) {
 }
 template <int N, int PC>
 constexpr bool direct_ok() {
-    return PC > 0 && N > 0 && (N & (N - 1)) == 0 && N >= 64 && (PC * (N / 8)) % FT == 0 &&
-           (PC * (N / radix_rt(N / last_stride(N)))) % FT == 0 && (FT % PC) == 0;
+    return PC > 0 && N >= 32 && N % 8 == 0 && FT % PC == 0;
 }
 
 // First stage (stride 1, radix 8) of a transform, its inputs read from HBM:
 // pencil i of the group is g[z * rs + i], z = 0 .. N-1.
 template <typename T, int N, int PC, bool INV>
 __device__ __forceinline__ void stage_first_from_hbm(cpx<T>* a, int ld, const cpx<T>* __restrict__ g, long rs) {
-    constexpr int R = radix_of<N>(), nR = N / R, NB = PC * nR / FT;
-    static_assert(R == 8 && PC * nR == NB * FT, "group shape");
+    constexpr int R = radix_of<N>(), nR = N / R, NB = (PC * nR + FT - 1) / FT;
+    constexpr bool EXACT = PC * nR == NB * FT;
+    static_assert(R == 8, "radix-8 first stage");
     cpx<T> v[NB][R];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int b = threadIdx.x + q * FT, pen = b % PC, j = b / PC;
+        if (EXACT || b < PC * nR) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = gld(g + (long)(j + r * nR) * rs + pen);
+            for (int r = 0; r < R; ++r) v[q][r] = gld(g + (long)(j + r * nR) * rs + pen);
+        }
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int b = threadIdx.x + q * FT, pen = b % PC, j = b / PC;
-        dft_small<T, R, INV>(v[q]);
-        cpx<T>* o = a + pen * ld + pad(j * R);  // stride 1: outputs j R + r
+        if (EXACT || b < PC * nR) {
+            dft_small<T, R, INV>(v[q]);
+            cpx<T>* o = a + pen * ld + pad(j * R);  // stride 1: outputs j R + r, one 8-element block
 #pragma unroll
-        for (int r = 0; r < R; ++r) o[r] = v[q][r];
+            for (int r = 0; r < R; ++r) o[r] = v[q][r];
+        }
     }
     __syncthreads();
 }
@@ -607,29 +611,35 @@ __device__ __forceinline__ void stage_first_from_hbm(cpx<T>* a, int ld, const cp
 // mode (kx0 + i, ky, m)).
 template <typename T, int N, int PC, typename G>
 __device__ __forceinline__ void stage_first_green(cpx<T>* a, int ld, G&& green) {
-    constexpr int R = radix_of<N>(), nR = N / R, NB = PC * nR / FT;
-    static_assert(R == 8 && PC * nR == NB * FT, "group shape");
+    constexpr int R = radix_of<N>(), nR = N / R, NB = (PC * nR + FT - 1) / FT;
+    constexpr bool EXACT = PC * nR == NB * FT;
+    static_assert(R == 8, "radix-8 first stage");
     cpx<T> v[NB][R];
     int dst[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int b = threadIdx.x + q * FT, pen = b / nR, j = b % nR;
-        const cpx<T>* src = a + pen * ld + pad(j);
+        dst[q] = -1;
+        if (EXACT || b < PC * nR) {
+            const cpx<T>* src = a + pen * ld;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const cpx<T> x = src[r * (nR + nR / 8)];  // element j + r nR
-            const T gf = green(pen, j + r * nR);
-            v[q][r] = mk<T>(x.x * gf, x.y * gf);
+            for (int r = 0; r < R; ++r) {
+                const cpx<T> x = src[pad(j + r * nR)];
+                const T gf = green(pen, j + r * nR);
+                v[q][r] = mk<T>(x.x * gf, x.y * gf);
+            }
+            dst[q] = pen * ld + pad(j * R);
         }
-        dst[q] = pen * ld + pad(j * R);
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        dft_small<T, R, true>(v[q]);
-        cpx<T>* o = a + dst[q];
+        if (EXACT || dst[q] >= 0) {
+            dft_small<T, R, true>(v[q]);
+            cpx<T>* o = a + dst[q];
 #pragma unroll
-        for (int r = 0; r < R; ++r) o[r] = v[q][r];
+            for (int r = 0; r < R; ++r) o[r] = v[q][r];
+        }
     }
     __syncthreads();
 }
@@ -649,11 +659,13 @@ __device__ __forceinline__ void stages_mid(cpx<T>* a, int ld, const cpx<T>* __re
 template <typename T, int N, int PC, bool INV>
 __device__ __forceinline__ void stage_last_to_hbm(const cpx<T>* a, int ld, const cpx<T>* __restrict__ tw,
                                                   cpx<T>* __restrict__ g, long rs) {
-    constexpr int NS = last_stride(N), R = N / NS, nR = N / R, NB = PC * nR / FT;
-    static_assert(PC * nR == NB * FT && nR == NS, "group shape");
+    constexpr int NS = last_stride(N), R = N / NS, nR = N / R, NB = (PC * nR + FT - 1) / FT;
+    constexpr bool EXACT = PC * nR == NB * FT;
+    static_assert(nR == NS, "last stage");
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int b = threadIdx.x + q * FT, pen = b % PC, k = b / PC;  // k = j: the stage's span is 1
+        if (!EXACT && b >= PC * nR) continue;
         const cpx<T>* src = a + pen * ld;
         cpx<T> v[R];
 #pragma unroll
