@@ -58,7 +58,7 @@ struct alignas(16) RecEK {
 // factor of the diffusive/migrative flux).
 template <typename T, int NS>
 struct EKConst {
-    T D[NS], hz[NS], ref[NS], ref2hz[NS];
+    T D[NS], hz[NS], ref[NS];
     T Es[13], Dc[NS][2];
 };
 
@@ -80,7 +80,6 @@ __device__ __forceinline__ EKConst<T, NS> ek_consts(const Sim<T>& s) {
         K.D[k] = (T)s.D[k];
         K.hz[k] = (T)(0.5 * s.z[k]);
         K.ref[k] = (T)s.rho_ref[k];
-        K.ref2hz[k] = (T)(0.5 * s.z[k]) * ((T)s.rho_ref[k] * (T)2);
     }
     return K;
 }
@@ -108,12 +107,14 @@ __device__ __forceinline__ T vof_frac(T ux, T uy, T uz) {
     return (vof_axis<T, SX>(ux) * vof_axis<T, SY>(uy)) * vof_axis<T, SZ>(uz);
 }
 
+// Fused multiply-add of the element type.
+__device__ __forceinline__ float fmt(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmt(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Flux on the link a -> b along half-direction H: total flux jt[k] and the
-// diffusive/migrative part divided by D, summed over species, in gsum.
-// CLEAN: neither end is a boundary cell and both have Psi = 0; the general
-// formula then reduces exactly (multiplications by 1 and additions of 0 are
-// exact) to the clean one, so both evaluations of a link give the same bits
-// whichever path they take.
+// diffusive/migrative part divided by D, summed over species, in gsum (the
+// general form: boundary cells and partial volumes; both cells of a link
+// evaluate it, from the same operands in the same order).
 // The advective fractions of one cell for every direction, from its nine
 // axis factors and their x-y pair products: g(s; u) = (f_x f_y) f_z, the same
 // operations in the same order as vof_frac, so both ends of a link still
@@ -138,52 +139,43 @@ struct VofCell {
 
 // ga = g(s; u_a), gb = g(-s; u_b) are passed in (one end's fractions come
 // from its VofCell).
-template <typename T, bool DEV, int NS, int H, bool CLEAN>
+template <typename T, bool DEV, int NS, int H>
 __device__ __forceinline__ void link_flux(const Sim<T>& s, const RecEK<T, NS>& a, const RecEK<T, NS>& b,
                                           const EKConst<T, NS>& K, const T ga, const T gb, T (&jt)[NS], T& gsum) {
-    if constexpr (!CLEAN) {
-        if (a.wall() || b.wall()) {
+    // Fused multiply-adds written out, none left to contraction: which
+    // product of x y - z w the compiler would fuse depends on the code around
+    // each inlined call, and the two cells of a link must round its flux alike.
+#pragma clang fp contract(off)
+    if (a.wall() || b.wall()) {
 #pragma unroll
-            for (int k = 0; k < NS; ++k) jt[k] = (T)0;
-            gsum = (T)0;
-            return;
-        }
+        for (int k = 0; k < NS; ++k) jt[k] = (T)0;
+        gsum = (T)0;
+        return;
     }
     const T dphi = (a.phi() - b.phi()) + K.Es[H];
-    T pa = (T)0, pb = (T)0, oa = (T)1, ob = (T)1;
-    if constexpr (!CLEAN) {
-        pa = s.pv ? a.psi() : (T)0;
-        pb = s.pv ? b.psi() : (T)0;
-        oa = (T)1 - pa;
-        ob = (T)1 - pb;
-    }
+    const T pa = s.pv ? a.psi() : (T)0, pb = s.pv ? b.psi() : (T)0;
+    const T oa = (T)1 - pa, ob = (T)1 - pb;
     const T dg = ga - gb;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         const T ra = a.r(k), rb = b.r(k);
-        T A, B;
-        if constexpr (CLEAN) {
-            A = ra - rb;
-            B = ra + rb;
-        } else {
-            A = ra * ob - rb * oa;
-            B = ra * ob + rb * oa;
-            if constexpr (DEV) A += K.ref[k] * (pa - pb);
-        }
-        T adv = ra * ga - rb * gb;
+        const T rbo = rb * oa;
+        T A = fmt(ra, ob, -rbo);
+        const T B = fmt(ra, ob, rbo);
+        if constexpr (DEV) A = fmt(K.ref[k], pa - pb, A);
+        T adv = fmt(ra, ga, -(rb * gb));
         T mig = K.hz[k] * B;
         if constexpr (DEV) {
-            // reference density terms: B += 2 ref (clean) or ref (oa + ob)
-            if constexpr (CLEAN) mig += K.ref2hz[k];
-            else mig += K.hz[k] * (K.ref[k] * (oa + ob));
-            adv += K.ref[k] * dg;
+            // reference density terms: B += ref (oa + ob)
+            mig = fmt(K.hz[k], K.ref[k] * (oa + ob), mig);
+            adv = fmt(K.ref[k], dg, adv);
         }
         if constexpr (H < 9) {
             // g = (A + mig dphi): the flux over D/(A0|s|); gsum collects it for
             // the friction, which the caller scales by 1/(A0|s|)
-            const T g = A + mig * dphi;
+            const T g = fmt(mig, dphi, A);
             gsum = k == 0 ? g : gsum + g;
-            jt[k] = K.Dc[k][hlen(H) > 1.0 ? 1 : 0] * g + adv;
+            jt[k] = fmt(K.Dc[k][hlen(H) > 1.0 ? 1 : 0], g, adv);
         } else {
             jt[k] = adv;
             gsum = (T)0;
@@ -314,10 +306,9 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
     return (bid % NXCD) * (n / NXCD) + bid / NXCD;
 }
 
-template <typename T, bool DEV, int NS, int TXW, int TYW, bool CLEAN>
-__device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T, NS, TXW, TYW>& sh, int s0, int sm,
-                                               int sp, int ctr, const EKConst<T, NS>& K, T (&dr)[NS], T (&fe)[3]) {
-    using SH = EKShared<T, NS, TXW, TYW>;
+template <typename T, bool DEV, int NS, typename SH>
+__device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const SH& sh, int s0, int sm, int sp, int ctr,
+                                               const EKConst<T, NS>& K, T (&dr)[NS], T (&fe)[3]) {
     const RecEK<T, NS> me = sh.get(s0, ctr);
     const VofCell<T> mv(me.ux(), me.uy(), me.uz());
     sfor<13>([&](auto HH) {
@@ -329,9 +320,9 @@ __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T
         const RecEK<T, NS> cu = sh.get(sup, up);
         const RecEK<T, NS> cd = sh.get(sdn, dn);
         T jt1[NS], jt2[NS], g1, g2;
-        link_flux<T, DEV, NS, h, CLEAN>(s, me, cu, K, mv.template frac<ox, oy, oz>(),
+        link_flux<T, DEV, NS, h>(s, me, cu, K, mv.template frac<ox, oy, oz>(),
                                         vof_frac<T, -ox, -oy, -oz>(cu.ux(), cu.uy(), cu.uz()), jt1, g1);
-        link_flux<T, DEV, NS, h, CLEAN>(s, cd, me, K, vof_frac<T, ox, oy, oz>(cd.ux(), cd.uy(), cd.uz()),
+        link_flux<T, DEV, NS, h>(s, cd, me, K, vof_frac<T, ox, oy, oz>(cd.ux(), cd.uy(), cd.uz()),
                                         mv.template frac<-ox, -oy, -oz>(), jt2, g2);
         // the first term of each sum is assigned (an added 0 is an instruction)
 #pragma unroll
@@ -353,9 +344,10 @@ __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T
     });
 }
 
-// Clean-window update gathered per neighbour (FP32 path).  The same fluxes as
+// Clean-window update gathered per neighbour.  The same fluxes as
 // ek_cell_update, summed in another order: for the neighbours n = a + d of
-// cell a (26 of them), with R = r + mean the full density,
+// cell a (26 of them), with R the full density (r + mean when DEV stores
+// deviations r from the mean, r itself otherwise),
 //   advective: the outgoing part, sum_d R_a g(d; u_a), is R_a (1 - g(0; u_a))
 //     (a cell's fractions over its 27 destinations add up to one), so only
 //     the incoming parts R_n g(-d; u_n) are gathered;
@@ -366,17 +358,16 @@ __device__ __forceinline__ void ek_cell_update(const Sim<T>& s, const EKShared<T
 // Each link's flux is then not rounded on its own, so the two cells of a link
 // no longer hand over bitwise equal amounts: the species totals move by the
 // rounding of each cell's sums, ~1e-7 of that cell's fluxes.
-template <int NS, int TXW, int TYW>
-__device__ __forceinline__ void ek_cell_update_gather(const EKShared<float, NS, TXW, TYW>& sh, int s0, int sm,
-                                                      int sp, int ctr, const EKConst<float, NS>& K,
-                                                      float (&dr)[NS], float (&fe)[3]) {
-    using SH = EKShared<float, NS, TXW, TYW>;
-    const RecEK<float, NS> me = sh.get(s0, ctr);
-    float G[NS][2], adv[NS], hzC[NS], F[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}}, gin = 0.0f;
+template <typename T, bool DEV, int NS, typename SH>
+__device__ __forceinline__ void ek_cell_update_gather(const SH& sh, int s0, int sm, int sp, int ctr,
+                                                      const EKConst<T, NS>& K, T (&dr)[NS], T (&fe)[3]) {
+    const RecEK<T, NS> me = sh.get(s0, ctr);
+    T G[NS][2], adv[NS], hzC[NS], F[2][3] = {{(T)0, (T)0, (T)0}, {(T)0, (T)0, (T)0}}, gin = (T)0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        G[k][0] = G[k][1] = adv[k] = 0.0f;
-        hzC[k] = K.hz[k] * (me.r(k) + K.ref[k] * 2.0f);  // z/2 (R_a + mean): the cell's share of z/2 (R_a + R_n)
+        G[k][0] = G[k][1] = adv[k] = (T)0;
+        // the cell's share of z/2 (R_a + R_n): z/2 (r_a + 2 mean) for deviations
+        hzC[k] = DEV ? K.hz[k] * (me.r(k) + K.ref[k] * (T)2) : K.hz[k] * me.r(k);
     }
     sfor<13>([&](auto HH) {
         constexpr int h = HH;
@@ -385,18 +376,18 @@ __device__ __forceinline__ void ek_cell_update_gather(const EKShared<float, NS, 
             constexpr int sg = SG;
             constexpr int dx = sg * hx(h), dy = sg * hy(h), dz = sg * hz(h);
             const int slot = dz == 0 ? s0 : (dz > 0 ? sp : sm);
-            const RecEK<float, NS> n = sh.get(slot, ctr + dy * SH::WX + dx);
-            const float gn = vof_frac<float, -dx, -dy, -dz>(n.ux(), n.uy(), n.uz());
+            const RecEK<T, NS> n = sh.get(slot, ctr + dy * SH::WX + dx);
+            const T gn = vof_frac<T, -dx, -dy, -dz>(n.ux(), n.uy(), n.uz());
             gin += gn;
 #pragma unroll
-            for (int k = 0; k < NS; ++k) adv[k] = __builtin_fmaf(n.r(k), gn, adv[k]);
+            for (int k = 0; k < NS; ++k) adv[k] = fmt(n.r(k), gn, adv[k]);
             if constexpr (h < 9) {
-                const float dphi = (me.phi() - n.phi()) + (sg > 0 ? K.Es[h] : -K.Es[h]);
-                float gs = 0.0f;
+                const T dphi = (me.phi() - n.phi()) + (sg > 0 ? K.Es[h] : -K.Es[h]);
+                T gs = (T)0;
 #pragma unroll
                 for (int k = 0; k < NS; ++k) {
-                    const float m = __builtin_fmaf(K.hz[k], n.r(k), hzC[k]);
-                    const float g = __builtin_fmaf(m, dphi, me.r(k) - n.r(k));
+                    const T m = fmt(K.hz[k], n.r(k), hzC[k]);
+                    const T g = fmt(m, dphi, me.r(k) - n.r(k));
                     G[k][c] += g;
                     gs = k == 0 ? g : gs + g;
                 }
@@ -416,20 +407,20 @@ __device__ __forceinline__ void ek_cell_update_gather(const EKShared<float, NS, 
     // there: a_x (a_y + b_y)(a_z + b_z) + b_x (a_y (a_z + b_z) + b_y a_z).
     // (1 - b_x b_y b_z would carry the rounding of each b_i, ~1e-8 absolute,
     // into every step's solute balance.)
-    const float ax = fabsf(me.ux()), ay = fabsf(me.uy()), az = fabsf(me.uz());
-    const float bx = vof_axis<float, 0>(me.ux()), by = vof_axis<float, 0>(me.uy()), bz = vof_axis<float, 0>(me.uz());
-    const float sz = az + bz;
-    const float out = __builtin_fmaf(ax, (ay + by) * sz, bx * __builtin_fmaf(ay, sz, by * az));
-    const float dg = gin - out;
+    const T ax = fabs(me.ux()), ay = fabs(me.uy()), az = fabs(me.uz());
+    const T bx = vof_axis<T, 0>(me.ux()), by = vof_axis<T, 0>(me.uy()), bz = vof_axis<T, 0>(me.uz());
+    const T sz = az + bz;
+    const T out = fmt(ax, (ay + by) * sz, bx * fmt(ay, sz, by * az));
+    const T dg = gin - out;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        float d = __builtin_fmaf(-me.r(k), out, adv[k]);
-        d = __builtin_fmaf(K.ref[k], dg, d);
-        d = __builtin_fmaf(-K.Dc[k][1], G[k][1], d);
-        dr[k] = __builtin_fmaf(-K.Dc[k][0], G[k][0], d);
+        T d = fmt(-me.r(k), out, adv[k]);
+        if constexpr (DEV) d = fmt(K.ref[k], dg, d);  // mean * (in - out)
+        d = fmt(-K.Dc[k][1], G[k][1], d);
+        dr[k] = fmt(-K.Dc[k][0], G[k][0], d);
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) fe[d] = __builtin_fmaf((float)link_coef<3>(), F[1][d], (float)link_coef<0>() * F[0][d]);
+    for (int d = 0; d < 3; ++d) fe[d] = fmt((T)link_coef<3>(), F[1][d], (T)link_coef<0>() * F[0][d]);
 }
 
 // Boundary-cell sources of one cell's populations from the staged flags.
@@ -523,12 +514,10 @@ __device__ __forceinline__ void ek_body(const Sim<T>& s, int bx_, int by_, int g
             T fe[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
             for (int k = 0; k < NS; ++k) dr[k] = (T)0;
-            if (clean) {
-                if constexpr (sizeof(T) == 4 && DEV) ek_cell_update_gather<NS, TXW, TYW>(sh, s0, sm, sp, ctr, K, dr, fe);
-                else ek_cell_update<T, DEV, NS, TXW, TYW, true>(s, sh, s0, sm, sp, ctr, K, dr, fe);
-            }
+            if (clean)
+                ek_cell_update_gather<T, DEV, NS>(sh, s0, sm, sp, ctr, K, dr, fe);
             else if (!wall)
-                ek_cell_update<T, DEV, NS, TXW, TYW, false>(s, sh, s0, sm, sp, ctr, K, dr, fe);
+                ek_cell_update<T, DEV, NS>(s, sh, s0, sm, sp, ctr, K, dr, fe);
             fe[0] *= half_kT;
             fe[1] *= half_kT;
             fe[2] *= half_kT;
@@ -669,9 +658,9 @@ __device__ __forceinline__ void ek_body_pipe(const Sim<float>& s, int bx_, int Z
 #pragma unroll
             for (int k = 0; k < NS; ++k) dr[k] = 0.0f;
             if (dm == 0)
-                ek_cell_update_gather<NS, TXW, TYW>(sh, s0, sm, sp, ctr, K, dr, fe);
+                ek_cell_update_gather<float, true, NS>(sh, s0, sm, sp, ctr, K, dr, fe);
             else if (!wall)
-                ek_cell_update<float, true, NS, TXW, TYW, false>(s, sh, s0, sm, sp, ctr, K, dr, fe);
+                ek_cell_update<float, true, NS>(s, sh, s0, sm, sp, ctr, K, dr, fe);
 #pragma unroll
             for (int k = 0; k < NS; ++k) out[k] = wall ? -K.ref[k] : sh.elem(s0, ctr, k) + dr[k];
         }
