@@ -6,13 +6,12 @@
 //   flux on each of its 26 links is evaluated (13 directions, both ends), the
 //   density changes by the flux divergence, and the coupling force on the fluid
 //   is the friction of the diffusive/migrative part (Eq. fluidcoupling).  In
-//   the general form (ek_cell_update: FP64, and FP32 windows holding a
-//   boundary cell or a partial volume) both cells of a link evaluate it with
-//   identical operands and operation order, so the two evaluations are
-//   bitwise equal and solute is conserved link by link; FP32 windows free of
-//   both gather the same fluxes per neighbour in fewer operations
-//   (ek_cell_update_gather), conserving solute to the rounding of each cell's
-//   sums.
+//   the general form (ek_cell_update: windows holding a boundary cell or a
+//   partial volume) both cells of a link evaluate it with identical operands
+//   and operation order, so the two evaluations are bitwise equal and solute
+//   is conserved link by link; windows free of both gather the same fluxes
+//   per neighbour in fewer operations (ek_cell_update_gather), conserving
+//   solute to the rounding of each cell's sums.
 //   Per link a -> b = a + s (s one of the 13 half-set directions):
 //     diffusive + migrative (the 9 D3Q19 links, Eq. flux-pv multiplied out):
 //       j = D/(A0|s|) [ rho_a(1-Psi_b) - rho_b(1-Psi_a)
