@@ -19,6 +19,10 @@ One JSON line is printed with the contract fields plus:
                    null once the kernel's sources differ from the measured ones;
   cpu_baseline  -- the FP64 CPU oracle timed on a few full steps (about 12 s)
                    of the same workload;
+  ek_alu        -- the FP32 EK kernel, bound by its vector ALU work: VALU
+                   instructions per launch from the stored SQ counter pass /
+                   its mean duration, against the issue peak (null once its
+                   sources differ from the measured ones);
   step_hbm      -- the whole FP32 step: HBM bytes of its kernels from the same
                    counter passes / the step time, against 8 TB/s (null once
                    any kernel source differs from the measured one);
@@ -48,6 +52,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Vector ALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD every 4 cycles (16 lanes
+# per SIMD; 39.3 T lane operations/s, 78.6 TFLOP/s of unpacked FP32 FMA -- half the packed 157.3).
+VALU_PEAK_GIPS = 256 * 4 * 2.4 / 4
 METRIC = "EK MLUPS + % HBM roofline, FP32 vs FP64 plain; p50/p99 latency in serve loop"
 
 
@@ -266,6 +273,12 @@ def main():
             "bytes_per_step": counters.stored_step_bytes(),
             "GBps": counters.stored_step_bytes() / (dt / args.steps) / 1e9,
             "frac": counters.stored_step_bytes() / (dt / args.steps) / 1e9 / HBM_PEAK_GBS},
+        "ek_alu": None if fp64 or counters.stored_valu() is None else {
+            "bound": "alu", "kernel": "k_ek32 (EK, FP32)", "unit": "G wave64 VALU instructions/s",
+            "achieved": counters.stored_valu()["valu_per_launch"] / (stages["ek"] * 1e-3) / 1e9,
+            "peak": VALU_PEAK_GIPS,
+            "frac": counters.stored_valu()["valu_per_launch"] / (stages["ek"] * 1e-3) / 1e9 / VALU_PEAK_GIPS,
+            "valu_per_launch": counters.stored_valu()["valu_per_launch"], "launch_ms": stages["ek"]},
         "kernels": {"stage_ms": stages, **{k: v for k, v in kern.items()},
                     "particle_frac": sum(stages[k] for k in PARTICLE_STAGES) / sum(stages.values())},
         "diagnostics": {"species_total": [float(x) for x in diag["species_total"][:len(w32.species)]],

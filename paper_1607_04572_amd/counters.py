@@ -14,6 +14,14 @@ Usage, from the repository root (cd /tmp && export TMPDIR=/tmp first):
       --steps 6 --warmup 2 --profile-steps 2 --no-cpu-baseline --no-fp64 --no-serve --copy-probe-mib 1024
   rocprofv3 --pmc WRITE_SIZE -d OUT/pmc_write -o run -- python <repo>/bench.py (same flags)
   python -m paper_1607_04572_amd.counters OUT/pmc_fetch/run_results.db OUT/pmc_write/run_results.db 1024
+
+The FP32 EK kernel is bound by its vector ALU work, not by HBM: its VALU
+instruction count per launch comes from an SQ counter pass of the same run
+(SQ_INSTS_VALU with SQ_WAVES), stored in counters_valu.json with a hash of the
+EK sources:
+
+  rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU -d OUT/pmc_sq -o run -- python <repo>/bench.py (same flags)
+  python -m paper_1607_04572_amd.counters --valu OUT/pmc_sq/run_results.db
 """
 from __future__ import annotations
 
@@ -31,6 +39,11 @@ SOURCES = ["csrc/ek_lb.h", "csrc/ek_lb.hip", "csrc/ek_internal.h"]
 # no measurable traffic), for the step-level figure; it holds while no kernel source has changed.
 STEP_KERNELS = ["k_lb<float", "k_ek32<", "k_fft_", "k_geometry<float", "k_boundary<float", "k_boundary_post<float",
                 "k_pool<float", "k_particle_forces<float", "k_finish<float"]
+
+
+VALU_STORE = os.path.join(HERE, "counters_valu.json")
+EK_KERNEL = "k_ek32<"
+EK_SOURCES = ["csrc/ek_fields.hip", "csrc/ek_lb.h", "csrc/ek_internal.h"]
 
 
 def source_hash(sources=None) -> str:
@@ -107,6 +120,29 @@ def stored_traffic() -> dict | None:
     return d if d.get("source_sha256") == source_hash() else None
 
 
+def store_valu(sq_db: str) -> dict:
+    """VALU instructions (wave64 instructions issued, all waves) and waves per launch of the FP32 EK kernel."""
+    valu = per_dispatch(sq_db, "SQ_INSTS_VALU")
+    waves = per_dispatch(sq_db, "SQ_WAVES")
+    out = {"kernel": EK_KERNEL, "source_sha256": source_hash(EK_SOURCES),
+           "valu_per_launch": pick(valu, EK_KERNEL), "waves_per_launch": pick(waves, EK_KERNEL)}
+    with open(VALU_STORE, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+def stored_valu() -> dict | None:
+    """The stored EK instruction count if it describes the current EK sources, else None."""
+    if not os.path.exists(VALU_STORE):
+        return None
+    with open(VALU_STORE) as f:
+        d = json.load(f)
+    return d if d.get("source_sha256") == source_hash(EK_SOURCES) else None
+
+
 if __name__ == "__main__":
-    r = main(sys.argv[1], sys.argv[2], int(sys.argv[3]))
-    print(json.dumps({k: v for k, v in r.items() if not k.startswith("all_")}, indent=1))
+    if sys.argv[1] == "--valu":
+        print(json.dumps(store_valu(sys.argv[2]), indent=1))
+    else:
+        r = main(sys.argv[1], sys.argv[2], int(sys.argv[3]))
+        print(json.dumps({k: v for k, v in r.items() if not k.startswith("all_")}, indent=1))
