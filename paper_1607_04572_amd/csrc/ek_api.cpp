@@ -1130,6 +1130,7 @@ struct ek_batch {
     bool dirty = true;
     hipGraphExec_t graph = nullptr;
     int graph_items[KK_N] = {};  // work items per kind the captured launches were sized for
+    bool refill = false, graph_refill = false;  // a live slot uses the simple scheme (now; when captured)
     int err = EK_OK;
 };
 
@@ -1268,8 +1269,10 @@ int push_table(ek_batch* b) {
         if (b->slot[i].used) n = i + 1;
     b->h.nsims = n;
     for (int k = 0; k < KK_N; ++k) b->h.start[k][0] = 0;
+    b->refill = false;
     for (int i = 0; i < MAX_SLOTS; ++i) {
         const bool live = i < n && b->slot[i].used && b->h.active[i];
+        if (live && !b->h.sims[i].pv) b->refill = true;
         b->h.keep[i] = b->slot[i].used && b->slot[i].on_device ? 1 : 0;
         if (i >= n) continue;
         Grids<float> g = grids_of<float>(b->h.sims[i]);
@@ -1292,7 +1295,7 @@ int push_table(ek_batch* b) {
 }
 
 void enqueue_batch_step(ek_batch* b, const int* items) {
-    launch_batch_particles_pre(b->dtab, items, b->stream);
+    launch_batch_particles_pre(b->dtab, items, b->refill, b->stream);
     launch_batch_poisson(b->dtab, items, b->stream);
     launch_batch_particle_forces(b->dtab, items, b->stream);
     launch_batch_fields(b->dtab, items, b->ns, b->stream);
@@ -1448,6 +1451,7 @@ int ek_batch_step(ek_batch* b, int k) {
         items[kk] = b->h.start[kk][b->h.nsims];
         same = same && items[kk] == b->graph_items[kk];
     }
+    same = same && b->refill == b->graph_refill;
     if (b->graph && !same) {
         // launches of the old graph may still be queued: destroyed once passed
         hipEvent_t ev = nullptr;
@@ -1465,6 +1469,7 @@ int ek_batch_step(ek_batch* b, int k) {
         (void)hipGraphDestroy(g);
         BCHK(b, e);
         for (int kk = 0; kk < KK_N; ++kk) b->graph_items[kk] = items[kk];
+        b->graph_refill = b->refill;
     }
     if (k == 0) return EK_OK;
     // at most two chunks ahead: the older one's snapshot is waited for (the

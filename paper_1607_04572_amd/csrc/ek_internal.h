@@ -394,7 +394,8 @@ template <typename T> void launch_finish(const Sim<T>& s, hipStream_t st, bool a
 template <typename T> void launch_diagnostics(const Sim<T>& s, hipStream_t st, double* out);
 // batched step pieces (FP32 tables); items[k] = total work items of kind k
 // over the table (start[k][nsims] of the table the launches will read)
-void launch_batch_particles_pre(const BatchTable* tab, const int* items, hipStream_t st);
+// refill: launch the simple scheme's refill kernels (some live slot uses that scheme)
+void launch_batch_particles_pre(const BatchTable* tab, const int* items, bool refill, hipStream_t st);
 void launch_batch_poisson(const BatchTable* tab, const int* items, hipStream_t st);
 void launch_batch_fields(const BatchTable* tab, const int* items, int ns, hipStream_t st);
 void launch_batch_particle_forces(const BatchTable* tab, const int* items, hipStream_t st);

@@ -1235,12 +1235,13 @@ __global__ void kb_finish(const BatchTable* __restrict__ tab) {
     batch_loop<KK_PRED>(tab, [](const Sim<float>& s, int b) { finish_body<float>(s, b, 0, 0); });
 }
 
-void launch_batch_particles_pre(const BatchTable* tab, const int* items, hipStream_t st) {
+void launch_batch_particles_pre(const BatchTable* tab, const int* items, bool refill, hipStream_t st) {
     hipLaunchKernelGGL(kb_move, dim3(BATCH_SMALL_BLOCKS), dim3(64), 0, st, tab);
     hipLaunchKernelGGL(kb_geometry, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_geometry, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
     hipLaunchKernelGGL(kb_boundary, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_boundary, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
     hipLaunchKernelGGL(kb_boundary_post, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_boundary_post, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
     hipLaunchKernelGGL(kb_pool, dim3(batch_grid(FLAT_PART, items[KK_POOL], (const void*)kb_pool, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
+    if (!refill) return;
     hipLaunchKernelGGL(kb_refill_vacated, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_refill_vacated, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
     hipLaunchKernelGGL(kb_refill_stable, dim3(batch_grid(FLAT_PART, items[KK_PART], (const void*)kb_refill_stable, PT, 0, BATCH_PART_BLOCKS)), dim3(PT), 0, st, tab);
 }

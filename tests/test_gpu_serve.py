@@ -83,6 +83,23 @@ def test_batch_equals_single_path():
     assert_same(batch, single)
 
 
+def test_simple_scheme_in_a_mix_equals_single_path():
+    """A simple-scheme request batched beside partial-volume ones (the batched
+    step then includes the refill kernels, which it leaves out while no live
+    request uses that scheme) gives the same bits as the single-simulation
+    path, and so does a partial-volume request of the same mix."""
+    say("case simple scheme in a mix")
+    S = A.replace(name="S", scheme="simple")
+    for target, w in (("S", S), ("B", B)):
+        batch = final_state_batch([B, S, C], 9, target=target)
+        g = EkSim(w, initial_density=W.initial_densities(w))
+        g.step(w.steps)
+        single = {f: g.field(f) for f in ("density", "populations", "phi", "velocity", "psi", "flag")}
+        single["particles"] = g.particles()
+        g.close()
+        assert_same(batch, single)
+
+
 def test_admission_by_footprint():
     say("case admission")
     from paper_1607_04572_amd.ek import ek_query_footprint, params_from_workload
