@@ -45,6 +45,34 @@ def test_poiseuille_exact_with_magic_parameter(nu):
     assert np.max(np.abs(u[:N])) < 1e-10 * ref.max() and np.max(np.abs(u[2 * N:])) < 1e-10 * ref.max()
 
 
+@pytest.mark.parametrize("nu", [1 / 6, 0.05])
+def test_couette_exact_with_a_moving_wall(nu):
+    """Velocity bounce-back (Sec. III.A): a plane of boundary cells at x = m
+    owned by a particle moving at (0, U, 0), a resting plane at x = 0, periodic
+    in x.  The steady profile of each channel is linear between the walls, which
+    sit half-way between nodes: u_y = U (x - 1/2) / (m - 1) between the resting
+    and the moving wall, U (nx - 1/2 - x) / (nx - m - 1) beyond.  A wrong sign
+    or factor of the wall term 6 w_i c_i.u_b, or the wall velocity of another
+    cell, moves the profile off the lines."""
+    nx, ny, nz, m = 14, 2, 2, 6
+    p = O.make_params(nx, ny, nz, nu, 1.0, 0.0, (0, 0, 0), [(0.1, 0)])
+    N = nx * ny * nz
+    x = np.tile(np.arange(nx), ny * nz)
+    flag = ((x == 0) | (x == m)).astype(np.uint8)
+    owner = np.where(x == m, 0, -1).astype(np.int32)
+    U = 1e-3
+    parts = [dict(x=(m + 0.5, 1.0, 1.0), R=0.5, Z=0.0, M=1.0, v=(0.0, U, 0.0), mode=1)]
+    f = np.tile(W19[:, None], (1, N)).reshape(-1)
+    f, u = run_lb(p, f, flag, owner, np.zeros(3 * N), 200000, parts=parts, tol=1e-19)
+    uy = u[N:2 * N]
+    a = (x > 0) & (x < m)
+    b = x > m
+    assert np.max(np.abs(uy[a] - U * (x[a] - 0.5) / (m - 1))) < 1e-9 * U
+    assert np.max(np.abs(uy[b] - U * (nx - 0.5 - x[b]) / (nx - m - 1))) < 1e-9 * U
+    fl = flag == 0
+    assert np.max(np.abs(u[:N][fl])) < 1e-9 * U and np.max(np.abs(u[2 * N:][fl])) < 1e-9 * U
+
+
 def test_rest_state_is_stationary():
     nx, ny, nz = 6, 5, 4
     N = nx * ny * nz
