@@ -456,16 +456,40 @@ __device__ __forceinline__ void geometry_body(const Sim<T>& s, int bx_, int by_,
     // resolved by a whole wavefront in turn, are then spread evenly over the
     // wavefronts instead of piling up in those whose cells lie on the surface.
     const int G = gx_ * PT, Wn = G / 64, wg = bx_ * (PT / 64) + wave;
-    for (int base = 0; base < me.ncell; base += G) {
-        int t = base + lane * Wn + wg;
-        int x = 0, y = 0, z = 0;
-        bool active = t < me.ncell;
-        if (active) {
-            bw.cell(s, t, x, y, z);
-            active = box_owner_is(s, L, p, x, y, z);
+    // The cell of the next round and its flag and owner are loaded before this
+    // round's stores (a cell is read and written only by the thread of its
+    // owning box, so the loads cannot see those stores), so that they do not
+    // wait behind them in the in-order memory counter.
+    struct Next {
+        int x, y, z;
+        bool active;
+        long c;
+        uint8_t flag;
+        uint16_t owner;
+    };
+    auto fetch = [&](int base) {
+        Next n{0, 0, 0, false, 0, 0, NO_OWNER};
+        const int t = base + lane * Wn + wg;
+        n.active = t < me.ncell;
+        if (n.active) {
+            bw.cell(s, t, n.x, n.y, n.z);
+            n.active = box_owner_is(s, L, p, n.x, n.y, n.z);
         }
-        long c = active ? cidx(s, x, y, z) : 0;
-        uint8_t old = active ? s.flag[c] : 0;
+        if (n.active) {
+            n.c = cidx(s, n.x, n.y, n.z);
+            n.flag = s.flag[n.c];
+            n.owner = s.owner[n.c];
+        }
+        return n;
+    };
+    Next nxt = fetch(0);
+    for (int base = 0; base < me.ncell; base += G) {
+        const Next here = nxt;
+        if (base + G < me.ncell) nxt = fetch(base + G);
+        const int x = here.x, y = here.y, z = here.z;
+        const bool active = here.active;
+        const long c = here.c;
+        const uint8_t old = here.flag;
         uint8_t wall = old & F_WALL;
         int cur = wall ? 1 : 0;
         uint16_t ow = NO_OWNER, pso = NO_OWNER;
@@ -505,7 +529,7 @@ __device__ __forceinline__ void geometry_body(const Sim<T>& s, int bx_, int by_,
         if (!active) continue;
         uint8_t prev = init ? (uint8_t)cur : (uint8_t)(old & F_CUR);
         s.flag[c] = (uint8_t)(wall | (cur ? F_CUR : 0) | (prev ? F_PREV : 0));
-        s.owner_prev[c] = init ? ow : s.owner[c];
+        s.owner_prev[c] = init ? ow : here.owner;
         s.owner[c] = ow;
         s.psi_owner[c] = pso;
         s.psi[c] = (float)(psum < 1.0 ? psum : 1.0);
