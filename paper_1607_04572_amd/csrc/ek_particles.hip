@@ -593,12 +593,32 @@ __device__ __forceinline__ void boundary_body(const Sim<T>& s, int bx_, int by_,
     // 0-2 Fc, 3-5 Tc, 6..6+MAXS pool, then counts
     double acc[6 + MAXS + 5];
     for (int k = 0; k < 6 + MAXS + 5; ++k) acc[k] = 0.0;
-    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += s.nchunk * PT) {
+    // the next cell's flag and owner (which this kernel does not write) are
+    // loaded before this cell's dependent loads
+    struct Next {
         int x, y, z;
-        bw.cell(s, t, x, y, z);
-        long c = cidx(s, x, y, z);
-        const uint8_t fl = s.flag[c];
-        const uint16_t own = s.owner[c];
+        long c;
+        uint8_t flag;
+        uint16_t owner;
+    };
+    auto fetch = [&](int t) {
+        Next n;
+        bw.cell(s, t, n.x, n.y, n.z);
+        n.c = cidx(s, n.x, n.y, n.z);
+        n.flag = s.flag[n.c];
+        n.owner = s.owner[n.c];
+        return n;
+    };
+    const int step = s.nchunk * PT;
+    Next nxt{};
+    if (bx_ * PT + (int)threadIdx.x < me.ncell) nxt = fetch(bx_ * PT + threadIdx.x);
+    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += step) {
+        const Next here = nxt;
+        if (t + step < me.ncell) nxt = fetch(t + step);
+        const int x = here.x, y = here.y, z = here.z;
+        const long c = here.c;
+        const uint8_t fl = here.flag;
+        const uint16_t own = here.owner;
         if ((fl & F_CUR) && own == p) acc[6 + MAXS + 3] += 1.0;  // n_b
         if ((fl & (F_CUR | F_PREV)) && !(fl & F_WALL) && box_owner_is(s, L, p, x, y, z)) acc[6 + MAXS + 4] += 1.0;
         if (stable(fl) && box_owner_is(s, L, p, x, y, z) && near_a_surface(s, L, x, y, z))
