@@ -894,12 +894,31 @@ __device__ __forceinline__ void hydro_force_body(const Sim<T>& s, int bx_, int b
     const BoxWalk bw(me);
     const T* f = s.f[s.cur];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += s.nchunk * PT) {
+    // the next cell's flag and owner are loaded before this cell's neighbour loads
+    struct Next {
         int x, y, z;
-        bw.cell(s, t, x, y, z);
-        long b = cidx(s, x, y, z);
-        const uint8_t fb = s.flag[b];
-        const uint16_t ob = s.owner[b];
+        long b;
+        uint8_t flag;
+        uint16_t owner;
+    };
+    auto fetch = [&](int t) {
+        Next n;
+        bw.cell(s, t, n.x, n.y, n.z);
+        n.b = cidx(s, n.x, n.y, n.z);
+        n.flag = s.flag[n.b];
+        n.owner = s.owner[n.b];
+        return n;
+    };
+    const int step = s.nchunk * PT;
+    Next nxt{};
+    if (bx_ * PT + (int)threadIdx.x < me.ncell) nxt = fetch(bx_ * PT + threadIdx.x);
+    for (int t = bx_ * PT + threadIdx.x; t < me.ncell; t += step) {
+        const Next here = nxt;
+        if (t + step < me.ncell) nxt = fetch(t + step);
+        const int x = here.x, y = here.y, z = here.z;
+        const long b = here.b;
+        const uint8_t fb = here.flag;
+        const uint16_t ob = here.owner;
         if (!(fb & F_CUR) || ob != p) continue;
         double r[3];
         cell_disp(s, x, y, z, me.x, r);
